@@ -1,0 +1,252 @@
+/*
+ * pgdto.h - C ABI of the MI355X (gfx950) projection library for PGD-TO
+ * (projected gradient descent for topology optimization, arXiv 2511.13905).
+ *
+ * What it computes.  Every entry point solves the projection subproblem of the
+ * paper: given a point y (the paper's rho~, the gradient step of Alg. 3), the
+ * box [lo, hi] (the paper's [l, u]) and m linearized constraint rows
+ * A x <= b (rows a_j = grad g_j(rho_t), Sec. 2.2, eq. (linearized)),
+ *
+ *     x = argmin 1/2 ||x - y||^2 + (1/(2 kappa)) ||s||^2
+ *         s.t. lo <= x <= hi,  A x - s <= b,  s >= 0,          kappa = 2/C
+ *
+ * (the regularized projection, eq. (regularized_projection); kappa = 0, i.e.
+ * C = INFINITY, is eq. (linearized) itself).  By Theorems 1 and 2 the answer is
+ * x = clip(y - A^T lam, lo, hi) for the unique multiplier lam >= 0 (lam is the
+ * paper's -y) with h(lam) <= 0 and lam_j h_j(lam) = 0, where
+ * h_j(lam) = a_j.x(lam) - b_j - kappa lam_j (Appendix A.2, eq. (h)).
+ *
+ *   PGDTO_SINGLE       one dense row: Algorithm 1 (dual bracket search).
+ *   PGDTO_INDEPENDENT  m rows on disjoint contiguous element ranges
+ *                      (Sec. 2.2.2): one bracket search per block, all blocks
+ *                      in one launch.
+ *   PGDTO_COUPLED      m <= PGDTO_MAX_M dense rows: Algorithm 2 (Stage 1
+ *                      single-active searches, then semismooth Newton with a
+ *                      line search, Appendix A.2).
+ *
+ * pgdto_pgd_step additionally performs one iteration body of Algorithm 3:
+ * step size (eq. final_alpha with the fallback rule), conjugate direction
+ * (eq. CG), rho~ = rho_t + omega alpha_t d_t, projection, stop test.
+ *
+ * Memory.  Pointers named "device" are HIP device memory (or memory the GPU
+ * can read), owned by the caller, 16-byte aligned.  Rows of A start on 16-byte
+ * boundaries: lda (in elements) must be >= n and lda * sizeof(T) a multiple of
+ * 16.  Outputs must not alias inputs except where stated.  The library never
+ * frees or retains caller buffers after a call returns (batch calls: until
+ * the request's poll returns PGDTO_OK or an error).
+ *
+ * Errors.  Every function returns a pgdto_status.  Argument errors are found
+ * on the host before anything is launched (PGDTO_ERR_ARG).  Numerical
+ * outcomes are reported in pgdto_result.outcome, never as a status.  No C++
+ * exception crosses this interface.
+ *
+ * Threads.  A context serializes its work on the stream it is called with;
+ * calls on one context must not overlap (use one context per stream).
+ * Batch submit/poll are thread-safe.
+ */
+#ifndef PGDTO_H
+#define PGDTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PGDTO_VERSION 1
+#define PGDTO_MAX_M 8        /* coupled rows */
+#define PGDTO_MAX_BLOCKS 64  /* independent blocks */
+
+typedef enum {
+  PGDTO_OK = 0,
+  PGDTO_PENDING = 1,           /* batch: request admitted, not finished    */
+  PGDTO_QUEUED = 2,            /* batch: request waiting for admission     */
+  PGDTO_ERR_ARG = -1,          /* invalid argument (nothing was launched)  */
+  PGDTO_ERR_HIP = -2,          /* HIP runtime error                        */
+  PGDTO_ERR_NOMEM = -3,        /* device or host allocation failed         */
+  PGDTO_ERR_UNKNOWN_TICKET = -4,
+  PGDTO_ERR_TIMEOUT = -5,      /* a device-side wait ran past its bound    */
+  PGDTO_ERR_BUSY = -6,         /* batch: queue full                        */
+  PGDTO_ERR_CANCELLED = -7     /* batch: destroyed before the request ran  */
+} pgdto_status;
+
+typedef enum {
+  PGDTO_CONVERGED = 0,   /* multiplier found to tolerance                       */
+  PGDTO_INACTIVE = 1,    /* lam = 0: x = clip(y) (Alg. 1 first branch)          */
+  PGDTO_INFEASIBLE = 2,  /* a row cannot hold on the box; kappa = 0: x is the
+                            saturated point, kappa > 0: positive slack          */
+  PGDTO_MAXITER = 3,     /* iteration limit reached; x is the last iterate      */
+  PGDTO_NONFINITE = 4    /* NaN/Inf in y or A; x is clip(y) and meaningless     */
+} pgdto_outcome;
+
+typedef enum { PGDTO_F32 = 0, PGDTO_F64 = 1 } pgdto_dtype;
+typedef enum { PGDTO_SINGLE = 0, PGDTO_INDEPENDENT = 1, PGDTO_COUPLED = 2 } pgdto_kind;
+
+/* 1-D dual search rule (Alg. 1 and Stage 1 of Alg. 2).
+ * BISECT: the printed midpoint rule.  NEWTON (default): the same bracket,
+ * but each pass also evaluates Newton points from both bracket ends of the
+ * piecewise-linear dual function (its slope sum_free a_i^2 + kappa comes
+ * out of the same pass), which reaches the exact root in a few passes.     */
+typedef enum { PGDTO_SEARCH_NEWTON = 0, PGDTO_SEARCH_BISECT = 1 } pgdto_search;
+
+/* Complementarity function of the semismooth Newton stage.
+ * PAPER: Phi_j = max(h_j, 0) + sign(max(-h_j, 0)) y_j as printed (eq. phi).
+ * CONTINUOUS (default): Phi_j = max(h_j, -c_j lam_j), c_j = (J_h)_jj; same
+ * roots, continuous at h_j = 0 (the printed form jumps there, which stalls
+ * the line search once h is at rounding level).                           */
+typedef enum { PGDTO_NCP_CONTINUOUS = 0, PGDTO_NCP_PAPER = 1 } pgdto_ncp;
+
+typedef enum { PGDTO_CG_PR_PLUS = 0, PGDTO_CG_FR = 1, PGDTO_CG_NONE = 2 } pgdto_cg_rule;
+
+typedef struct {
+  int32_t kind;                 /* pgdto_kind                                   */
+  int32_t dtype;                /* pgdto_dtype of y, A and x                    */
+  int64_t n;                    /* elements, n >= 1                             */
+  int32_t m;                    /* rows (SINGLE: 1; INDEPENDENT: blocks)        */
+  const void* y;                /* device [n]: point to project (rho~)          */
+  const void* A;                /* device: SINGLE/COUPLED [m][lda] row-major;
+                                   INDEPENDENT [n], coefficient of element i in
+                                   the row of the block that owns it            */
+  int64_t lda;                  /* SINGLE/COUPLED row stride (elements)         */
+  const int64_t* block_offsets; /* host [m+1], INDEPENDENT only:
+                                   0 = o_0 < o_1 < ... < o_m = n               */
+  const double* b;              /* host [m]: right-hand sides of A x <= b       */
+  double lo, hi;                /* box, finite, lo < hi                         */
+  double C;                     /* penalty; kappa = 2/C; INFINITY: kappa = 0   */
+  void* x;                      /* device [n] output; must not alias y or A    */
+  uint32_t* free_mask;          /* optional device [(n+31)/32]: bit i set when
+                                   lo <= (y - A^T lam)_i <= hi; NULL to skip    */
+} pgdto_problem;
+
+typedef struct {
+  double tol_b;          /* bracket width at which a 1-D search stops (absolute,
+                            dual units; paper default 1e-8, Sec. 2.5)        */
+  double tol_n;          /* residual tolerance relative to each row's scale
+                            sigma_j = sum_i |a_ji| max(|lo|,|hi|); default
+                            1e-12 (the paper's 1e-6 is absolute)             */
+  int32_t max_search;    /* passes of one 1-D search (default 64)            */
+  int32_t max_newton;    /* Newton iterations (default 50)                   */
+  int32_t max_ls;        /* line-search trials per iteration (default 12)    */
+  int32_t search;        /* pgdto_search                                     */
+  int32_t ncp;           /* pgdto_ncp                                        */
+  int32_t stage1;        /* COUPLED: 1 = run Stage 1 (default), 0 = skip      */
+  double c1, c2;         /* Armijo / curvature constants (1e-4, 0.9)         */
+} pgdto_params;
+
+typedef struct {
+  int32_t outcome;       /* pgdto_outcome, worst over rows/blocks            */
+  int32_t path;          /* 0 box only, 1 bracket search, 2 Stage-1 exit,
+                            3 Newton                                         */
+  int32_t passes;        /* streaming passes over y and A (incl. final)      */
+  int32_t iters_search;  /* 1-D search passes (max over rows/blocks)         */
+  int32_t iters_newton;  /* Newton iterations                                */
+  int32_t iters_ls;      /* line-search trials (Newton passes)               */
+  int32_t m;             /* rows / blocks                                    */
+  int32_t error;         /* 0, or PGDTO_ERR_TIMEOUT if a device wait expired */
+  int64_t n_free;        /* elements with lo <= z_i <= hi                    */
+  double lambda[PGDTO_MAX_BLOCKS];  /* multipliers (>= 0)                    */
+  double resid[PGDTO_MAX_BLOCKS];   /* a_j.x - b_j with x as stored          */
+  double slack[PGDTO_MAX_BLOCKS];   /* kappa lam_j (eq. s_y_robust)          */
+  int32_t row_outcome[PGDTO_MAX_BLOCKS];
+  double res_inf;        /* max_j scaled KKT residual at exit                */
+  double lambda_width;   /* final bracket width (1-D searches, max)          */
+} pgdto_result;
+
+typedef struct {
+  pgdto_problem proj;    /* A = grad g(rho_t); proj.y and proj.b are ignored
+                            (formed on the device); proj.x receives rho_{t+1} */
+  const void* rho;       /* device [n] rho_t                                  */
+  const void* rho_prev;  /* device [n] rho_{t-1} (ignored at t = 0)           */
+  const void* grad;      /* device [n] grad f(rho_t)                          */
+  const void* grad_prev; /* device [n] grad f(rho_{t-1}) (ignored at t = 0)   */
+  void* dir;             /* device [n]: in d_{t-1}, out d_t (in place)        */
+  const double* g;       /* host [m] g_j(rho_t)                               */
+  const double* G;       /* host [m] bounds G_j                               */
+  int64_t t;             /* iteration index                                   */
+  int32_t t_warmup;      /* 50                                                */
+  int32_t cg_rule;       /* pgdto_cg_rule                                     */
+  double alpha_max;      /* 1e2                                               */
+  double alpha_fallback; /* 0.2                                               */
+  double omega;          /* 1.0                                               */
+  double eps_alpha;      /* 1e-6                                              */
+  double tol_viol;       /* tol_N of the fallback rule (1e-6)                 */
+  double tol;            /* stop test ||rho_{t+1}-rho_t|| / ||rho_{t+1}||     */
+} pgdto_pgd_args;
+
+typedef struct {
+  double alpha, beta;    /* step size and conjugate coefficient used          */
+  double rel_change;     /* ||rho_{t+1} - rho_t||_2 / ||rho_{t+1}||_2         */
+  int32_t used_fallback; /* 1 if alpha = min(alpha_max, alpha_fb/||grad||_inf)*/
+  int32_t converged;     /* rel_change <= tol                                 */
+  pgdto_result proj;     /* the projection's result (x = rho_{t+1})           */
+} pgdto_pgd_out;
+
+typedef struct pgdto_ctx pgdto_ctx;
+typedef struct pgdto_batch pgdto_batch;
+
+/* Defaults listed above (paper Sec. 2.5 where the paper fixes them). */
+void pgdto_params_default(pgdto_params* p);
+void pgdto_pgd_args_default(pgdto_pgd_args* a);
+
+/* Create a context on HIP device `device`: allocates the fixed workspace
+ * (per-tile partial sums, barrier words, result staging) once. */
+int pgdto_ctx_create(int device, pgdto_ctx** out);
+int pgdto_ctx_destroy(pgdto_ctx* ctx);
+
+/* Project (Alg. 1 / Alg. 2).  Enqueues one cooperative launch on `stream`
+ * and waits for it; *out is filled on return.  params may be NULL. */
+int pgdto_project(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params,
+                  pgdto_result* out, void* stream);
+
+/* Same, without waiting: the result struct is written to `result_dev`
+ * (device memory, sizeof(pgdto_result) bytes, caller-owned) when the launch
+ * completes in stream order.  Host arrays (b, block_offsets) are read before
+ * the call returns. */
+int pgdto_project_async(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params,
+                        pgdto_result* result_dev, void* stream);
+
+/* One body of Algorithm 3 (step size, direction, rho~, projection, stop test),
+ * one cooperative launch; waits and fills *out. */
+int pgdto_pgd_step(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,
+                   pgdto_pgd_out* out, void* stream);
+int pgdto_pgd_step_async(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,
+                         pgdto_pgd_out* out_dev, void* stream);
+
+/* Serving: continuous batching of projection requests. */
+typedef struct {
+  size_t hbm_budget_bytes;   /* admission limit on the summed footprint of the
+                                requests in flight (0: 90% of free memory)    */
+  int32_t max_slots;         /* concurrent requests on the device (0: auto)   */
+  int32_t wg_per_slot;       /* workgroups per slot (0: auto)                 */
+  int32_t queue_capacity;    /* pending requests (0: 65536)                   */
+} pgdto_batch_cfg;
+
+int pgdto_batch_create(pgdto_ctx* ctx, const pgdto_batch_cfg* cfg, pgdto_batch** out);
+/* Non-blocking.  The problem's device buffers must stay valid until poll
+ * returns PGDTO_OK or an error for this ticket.  Host arrays are copied. */
+int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, const pgdto_params* params,
+                       uint64_t* ticket);
+/* PGDTO_QUEUED / PGDTO_PENDING / PGDTO_OK (result copied, ticket retired) /
+ * error.  Thread-safe. */
+int pgdto_batch_poll(pgdto_batch* b, uint64_t ticket, pgdto_result* out);
+/* Blocks until the ticket finishes (or errors). */
+int pgdto_batch_wait(pgdto_batch* b, uint64_t ticket, pgdto_result* out);
+/* Statistics: admitted, completed, queued, in flight, peak footprint. */
+int pgdto_batch_stats(pgdto_batch* b, int64_t* admitted, int64_t* completed, int64_t* queued,
+                      int64_t* in_flight, int64_t* peak_bytes);
+/* Cancels queued requests, waits for in-flight ones, releases resources. */
+int pgdto_batch_destroy(pgdto_batch* b);
+
+const char* pgdto_status_string(int status);
+int pgdto_version(void);
+
+/* Layout introspection for language bindings: sizeof of the public structs.
+ * which: 0 pgdto_problem, 1 pgdto_params, 2 pgdto_result, 3 pgdto_pgd_args,
+ * 4 pgdto_pgd_out, 5 pgdto_batch_cfg.  Returns 0 for an unknown index. */
+size_t pgdto_struct_size(int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PGDTO_H */

@@ -72,10 +72,15 @@ def cg_beta(grad, grad_prev, t, rule="pr+"):
 
 
 def pgd_step(kind, rho, rho_prev, grad, grad_prev, d_prev, A, g, G, t, lo, hi,
-             C=math.inf, offsets=None, p: PgdParams | None = None):
+             C=math.inf, offsets=None, p: PgdParams | None = None, stream_dtype=None):
     """One iteration body of Alg. 3: alpha_t, beta_t, d_t = -grad + beta d_{t-1},
     rho~ = rho_t + omega alpha_t d_t, rho_{t+1} = projection of rho~, and the
-    relative-change stop test.  All arithmetic in float64."""
+    relative-change stop test.  All arithmetic in float64.
+
+    ``stream_dtype``: the precision in which rho~ is stored before it is
+    projected (the paper does not fix one).  With float32 streams rho~ is a
+    float32 array like any other input of the projection, so it is rounded
+    once here; everything else stays float64."""
     p = p or PgdParams()
     f64 = lambda v: np.asarray(v, dtype=np.float64)
     rho, rho_prev, grad, grad_prev, d_prev = map(f64, (rho, rho_prev, grad, grad_prev, d_prev))
@@ -85,6 +90,8 @@ def pgd_step(kind, rho, rho_prev, grad, grad_prev, d_prev, A, g, G, t, lo, hi,
     beta = cg_beta(grad, grad_prev, t, p.cg_rule)
     d = -grad + beta * d_prev
     rho_t = rho + p.omega * alpha * d
+    if stream_dtype is not None and np.dtype(stream_dtype) != np.float64:
+        rho_t = rho_t.astype(stream_dtype).astype(np.float64)
     if kind == "independent":
         c = f64(A).reshape(-1)
         arho = np.array([fsum(c[int(offsets[j]):int(offsets[j + 1])] * rho[int(offsets[j]):int(offsets[j + 1])])

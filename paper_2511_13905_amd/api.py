@@ -1,0 +1,227 @@
+"""Python binding of the projection library (same names as the C ABI).
+
+Torch tensors provide device memory and streams; the binding only marshals
+pointers and sizes into the structs of include/pgdto.h.  Every step of the
+projection runs in the HIP kernels of libpgdto.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import torch
+
+from . import _native as N
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return N.F32
+    if t.dtype == torch.float64:
+        return N.F64
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _check(st: int, where: str):
+    if st != N.OK:
+        raise N.PgdtoError(st, where)
+
+
+def make_params(**kw) -> N.Params:
+    """pgdto_params with the library defaults, overridden by keyword."""
+    p = N.Params()
+    N.lib().pgdto_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "search" and isinstance(v, str):
+            v = {"newton": N.SEARCH_NEWTON, "bisect": N.SEARCH_BISECT}[v]
+        if k == "ncp" and isinstance(v, str):
+            v = {"continuous": N.NCP_CONTINUOUS, "paper": N.NCP_PAPER}[v]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def aligned_rows(A: torch.Tensor) -> torch.Tensor:
+    """Return A ([m, n]) with rows on 16-byte boundaries (pads the row stride)."""
+    A = A if A.dim() == 2 else A.reshape(1, -1)
+    m, n = A.shape
+    esz = A.element_size()
+    vec = 16 // esz
+    if A.stride(1) == 1 and (A.stride(0) * esz) % 16 == 0 and A.data_ptr() % 16 == 0 and A.stride(0) >= n:
+        return A
+    lda = (n + vec - 1) // vec * vec
+    buf = torch.zeros((m, lda), dtype=A.dtype, device=A.device)
+    buf[:, :n].copy_(A)
+    return buf[:, :n]
+
+
+class _Keep:
+    """Holds host arrays referenced by a struct until the call returns."""
+
+    def __init__(self):
+        self.refs = []
+
+    def dbl(self, vals):
+        arr = (C.c_double * max(1, len(vals)))(*[float(v) for v in vals])
+        self.refs.append(arr)
+        return arr
+
+    def i64(self, vals):
+        arr = (C.c_int64 * len(vals))(*[int(v) for v in vals])
+        self.refs.append(arr)
+        return arr
+
+
+def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, free_mask=None,
+                   keep: _Keep | None = None):
+    """Fill a pgdto_problem from torch tensors; returns (struct, x, A_used)."""
+    keep = keep or _Keep()
+    k = N.KINDS[kind] if isinstance(kind, str) else int(kind)
+    if y is not None and not y.is_contiguous():
+        raise ValueError("y must be contiguous")
+    ref = y if y is not None else x
+    n = ref.numel()
+    if k == N.INDEPENDENT:
+        A_used = A.reshape(-1)
+        if not A_used.is_contiguous():
+            raise ValueError("independent coefficients must be contiguous")
+        m = len(offsets) - 1
+        lda = n
+    else:
+        A_used = aligned_rows(A)
+        m = A_used.shape[0]
+        lda = A_used.stride(0) if m > 1 else n
+    if x is None:
+        x = torch.empty(n, dtype=ref.dtype, device=ref.device)
+    s = N.Problem()
+    s.kind = k
+    s.dtype = _dtype_code(ref)
+    s.n = n
+    s.m = m
+    s.y = y.data_ptr() if y is not None else None
+    s.A = A_used.data_ptr()
+    s.lda = lda
+    s.block_offsets = keep.i64(offsets) if offsets is not None else None
+    s.b = keep.dbl(list(b)) if b is not None else None
+    s.lo = float(lo)
+    s.hi = float(hi)
+    s.C = float(C_pen)
+    s.x = x.data_ptr()
+    s.free_mask = free_mask.data_ptr() if free_mask is not None else None
+    return s, x, A_used
+
+
+def _stream(device, stream):
+    if stream is None:
+        return torch.cuda.current_stream(device).cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Context:
+    """pgdto_ctx: fixed workspace on one device (create once, reuse)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(N.lib().pgdto_ctx_create(device, C.byref(h)), "pgdto_ctx_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().pgdto_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ projection
+    def project(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None,
+                params: N.Params | dict | None = None, stream=None):
+        """pgdto_project: returns (x, result dict).  Blocks until done."""
+        keep = _Keep()
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        r = N.Result()
+        st = N.lib().pgdto_project(self.h, C_byref(s), C_byref(p), C_byref(r), _stream(self.device, stream))
+        _check(st, "pgdto_project")
+        return x, r.to_dict()
+
+    def project_async(self, kind, y, A, b, lo, hi, result_buf: torch.Tensor, C=math.inf, offsets=None,
+                      x=None, free_mask=None, params=None, stream=None):
+        """pgdto_project_async: enqueue only; the result struct lands in result_buf
+        (uint8 device tensor of at least sizeof(pgdto_result) bytes)."""
+        keep = _Keep()
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        st = N.lib().pgdto_project_async(self.h, C_byref(s), C_byref(p), result_buf.data_ptr(),
+                                         _stream(self.device, stream))
+        _check(st, "pgdto_project_async")
+        return x
+
+    # ------------------------------------------------------------ Alg. 3 step
+    def _pgd_struct(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
+                    hyper, keep):
+        s, x, _A = problem_struct(kind, None, A, None, lo, hi, C, offsets, x if x is not None else
+                                  torch.empty_like(rho), None, keep)
+        a = N.PgdArgs()
+        N.lib().pgdto_pgd_args_default(C_byref(a))
+        a.proj = s
+        a.rho = rho.data_ptr()
+        a.rho_prev = rho_prev.data_ptr() if rho_prev is not None else None
+        a.grad = grad.data_ptr()
+        a.grad_prev = grad_prev.data_ptr() if grad_prev is not None else None
+        a.dir = d.data_ptr()
+        a.g = keep.dbl(list(g))
+        a.G = keep.dbl(list(G))
+        a.t = int(t)
+        for k, v in (hyper or {}).items():
+            if k == "cg_rule" and isinstance(v, str):
+                v = N.CG_RULES[v]
+            setattr(a, k, v)
+        return a, x
+
+    def pgd_step(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf,
+                 offsets=None, x=None, params=None, stream=None, **hyper):
+        """pgdto_pgd_step: one Alg. 3 body.  d is updated in place (d_{t-1} -> d_t);
+        returns (rho_{t+1}, out dict)."""
+        keep = _Keep()
+        a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
+                                hyper, keep)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        out = N.PgdOut()
+        st = N.lib().pgdto_pgd_step(self.h, C_byref(a), C_byref(p), C_byref(out), _stream(self.device, stream))
+        _check(st, "pgdto_pgd_step")
+        return x, out.to_dict()
+
+    def pgd_step_async(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, out_buf,
+                       C=math.inf, offsets=None, x=None, params=None, stream=None, **hyper):
+        keep = _Keep()
+        a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
+                                hyper, keep)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        st = N.lib().pgdto_pgd_step_async(self.h, C_byref(a), C_byref(p), out_buf.data_ptr(),
+                                          _stream(self.device, stream))
+        _check(st, "pgdto_pgd_step_async")
+        return x
+
+
+def C_byref(obj):
+    return C.byref(obj)
+
+
+def result_from_bytes(buf: torch.Tensor, pgd: bool = False) -> dict:
+    """Decode a result struct copied back from device memory (uint8 tensor)."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    S = N.PgdOut if pgd else N.Result
+    obj = S.from_buffer_copy(raw[:C.sizeof(S)])
+    return obj.to_dict()
+
+
+def result_nbytes(pgd: bool = False) -> int:
+    return C.sizeof(N.PgdOut if pgd else N.Result)

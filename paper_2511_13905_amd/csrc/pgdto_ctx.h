@@ -1,0 +1,23 @@
+// The context object behind pgdto_ctx* (host library internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pgdto_internal.h"
+
+struct pgdto_ctx {
+  int device = 0;
+  double* part = nullptr;        // per-tile partial sums, double-buffered
+  uint32_t* bar = nullptr;       // grid-barrier words
+  void* res_dev = nullptr;       // device staging of a result struct
+  void* res_host = nullptr;      // pinned host staging
+  int coop_cap[2][2][PGDTO_MAX_M + 1] = {};   // co-resident workgroups per kernel
+  int last_grid = 0;
+  int last_ntiles = 0;
+};
+
+namespace pgdto {
+int validate_params(const pgdto_params* p);
+int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Desc& d);
+int grid_for(pgdto_ctx* c, const Desc& d);
+}  // namespace pgdto

@@ -1,0 +1,354 @@
+// Host side of the C ABI: argument validation, tiling, cooperative launch,
+// result retrieval.  No allocation happens on the call path: the context owns
+// a fixed workspace sized for the largest tile table.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "pgdto_internal.h"
+#include "pgdto_ctx.h"
+
+using namespace pgdto;
+
+extern "C" void pgdto_params_default(pgdto_params* p) {
+  if (!p) return;
+  p->tol_b = 1e-8;
+  p->tol_n = 1e-12;
+  p->max_search = 64;
+  p->max_newton = 50;
+  p->max_ls = 12;
+  p->search = PGDTO_SEARCH_NEWTON;
+  p->ncp = PGDTO_NCP_CONTINUOUS;
+  p->stage1 = 1;
+  p->c1 = 1e-4;
+  p->c2 = 0.9;
+}
+
+extern "C" void pgdto_pgd_args_default(pgdto_pgd_args* a) {
+  if (!a) return;
+  memset(a, 0, sizeof(*a));
+  a->proj.kind = PGDTO_SINGLE;
+  a->proj.dtype = PGDTO_F32;
+  a->proj.lo = 1e-3;
+  a->proj.hi = 1.0;
+  a->proj.C = INFINITY;
+  a->t_warmup = 50;
+  a->cg_rule = PGDTO_CG_PR_PLUS;
+  a->alpha_max = 1e2;
+  a->alpha_fallback = 0.2;
+  a->omega = 1.0;
+  a->eps_alpha = 1e-6;
+  a->tol_viol = 1e-6;
+  a->tol = 1e-4;
+}
+
+extern "C" const char* pgdto_status_string(int s) {
+  switch (s) {
+    case PGDTO_OK: return "ok";
+    case PGDTO_PENDING: return "pending";
+    case PGDTO_QUEUED: return "queued";
+    case PGDTO_ERR_ARG: return "invalid argument";
+    case PGDTO_ERR_HIP: return "HIP runtime error";
+    case PGDTO_ERR_NOMEM: return "out of memory";
+    case PGDTO_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    case PGDTO_ERR_TIMEOUT: return "device wait timed out";
+    case PGDTO_ERR_BUSY: return "queue full";
+    case PGDTO_ERR_CANCELLED: return "cancelled";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int pgdto_version(void) { return PGDTO_VERSION; }
+
+extern "C" size_t pgdto_struct_size(int which) {
+  switch (which) {
+    case 0: return sizeof(pgdto_problem);
+    case 1: return sizeof(pgdto_params);
+    case 2: return sizeof(pgdto_result);
+    case 3: return sizeof(pgdto_pgd_args);
+    case 4: return sizeof(pgdto_pgd_out);
+    case 5: return sizeof(pgdto_batch_cfg);
+    default: return 0;
+  }
+}
+
+extern "C" int pgdto_ctx_create(int device, pgdto_ctx** out) {
+  if (!out) return PGDTO_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PGDTO_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return PGDTO_ERR_HIP;
+  pgdto_ctx* c = new (std::nothrow) pgdto_ctx();
+  if (!c) return PGDTO_ERR_NOMEM;
+  c->device = device;
+  int ok = hipMalloc(&c->part, sizeof(double) * PART_DOUBLES) == hipSuccess;
+  ok = ok && hipMalloc(&c->bar, 64 * sizeof(uint32_t)) == hipSuccess;
+  ok = ok && hipMalloc(&c->res_dev, sizeof(pgdto_pgd_out)) == hipSuccess;
+  ok = ok && hipHostMalloc(&c->res_host, sizeof(pgdto_pgd_out), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMemset(c->bar, 0, 64 * sizeof(uint32_t)) == hipSuccess;
+  ok = ok && hipMemset(c->part, 0, sizeof(double) * PART_DOUBLES) == hipSuccess;
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    pgdto_ctx_destroy(c);
+    return PGDTO_ERR_NOMEM;
+  }
+  *out = c;
+  return PGDTO_OK;
+}
+
+extern "C" int pgdto_ctx_destroy(pgdto_ctx* c) {
+  if (!c) return PGDTO_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->part) (void)hipFree(c->part);
+  if (c->bar) (void)hipFree(c->bar);
+  if (c->res_dev) (void)hipFree(c->res_dev);
+  if (c->res_host) (void)hipHostFree(c->res_host);
+  delete c;
+  return PGDTO_OK;
+}
+
+namespace pgdto {
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + na, b0 = (uintptr_t)b, b1 = b0 + nb;
+  return a0 < b1 && b0 < a1;
+}
+
+int validate_params(const pgdto_params* p) {
+  if (!(p->tol_n > 0.0) || !(p->tol_b >= 0.0)) return PGDTO_ERR_ARG;
+  if (p->max_search < 1 || p->max_newton < 1 || p->max_ls < 1) return PGDTO_ERR_ARG;
+  if (p->search != PGDTO_SEARCH_NEWTON && p->search != PGDTO_SEARCH_BISECT) return PGDTO_ERR_ARG;
+  if (p->ncp != PGDTO_NCP_CONTINUOUS && p->ncp != PGDTO_NCP_PAPER) return PGDTO_ERR_ARG;
+  if (!(p->c1 > 0.0 && p->c1 < 1.0 && p->c2 > p->c1 && p->c2 < 1.0)) return PGDTO_ERR_ARG;
+  return PGDTO_OK;
+}
+
+// Validates a problem (host side only; nothing is launched on failure) and
+// fills the problem part of the descriptor, including the tile table.
+// need_y: the problem's y pointer is used (not for pgd_step).
+int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Desc& d) {
+  memset(&d, 0, sizeof(d));
+  if (!pr || !pp) return PGDTO_ERR_ARG;
+  if (validate_params(pp) != PGDTO_OK) return PGDTO_ERR_ARG;
+  if (pr->dtype != PGDTO_F32 && pr->dtype != PGDTO_F64) return PGDTO_ERR_ARG;
+  if (pr->n < 1) return PGDTO_ERR_ARG;
+  const size_t esz = pr->dtype == PGDTO_F32 ? 4 : 8;
+  const int64_t n = pr->n;
+  switch (pr->kind) {
+    case PGDTO_SINGLE: if (pr->m != 1) return PGDTO_ERR_ARG; break;
+    case PGDTO_INDEPENDENT: if (pr->m < 1 || pr->m > PGDTO_MAX_BLOCKS) return PGDTO_ERR_ARG; break;
+    case PGDTO_COUPLED: if (pr->m < 1 || pr->m > PGDTO_MAX_M) return PGDTO_ERR_ARG; break;
+    default: return PGDTO_ERR_ARG;
+  }
+  if ((need_y && !pr->y) || !pr->A || !pr->x || !pr->b) return PGDTO_ERR_ARG;
+  if ((need_y && !aligned16(pr->y)) || !aligned16(pr->A) || !aligned16(pr->x)) return PGDTO_ERR_ARG;
+  if (pr->free_mask && ((uintptr_t)pr->free_mask & 3u)) return PGDTO_ERR_ARG;
+  if (!isfinite(pr->lo) || !isfinite(pr->hi) || !(pr->lo < pr->hi)) return PGDTO_ERR_ARG;
+  if (!(pr->C > 0.0)) return PGDTO_ERR_ARG;     // NaN and non-positive rejected; INFINITY allowed
+  size_t abytes = (size_t)n * esz;
+  if (pr->kind != PGDTO_INDEPENDENT) {
+    if (pr->m > 1) {
+      if (pr->lda < n || ((size_t)pr->lda * esz) % 16 != 0) return PGDTO_ERR_ARG;
+    }
+    abytes = ((size_t)(pr->m - 1) * (size_t)std::max<int64_t>(pr->lda, n) + (size_t)n) * esz;
+  }
+  const size_t xbytes = (size_t)n * esz;
+  if ((need_y && overlaps(pr->x, xbytes, pr->y, xbytes)) || overlaps(pr->x, xbytes, pr->A, abytes))
+    return PGDTO_ERR_ARG;
+  for (int j = 0; j < pr->m; ++j)
+    if (!isfinite(pr->b[j])) return PGDTO_ERR_ARG;
+
+  d.kind = pr->kind;
+  d.dtype = pr->dtype;
+  d.m = pr->m;
+  d.n = n;
+  d.lda = pr->kind == PGDTO_INDEPENDENT ? n : (pr->m > 1 ? pr->lda : std::max<int64_t>(pr->lda, n));
+  d.y = pr->y;
+  d.A = pr->A;
+  d.x = pr->x;
+  d.free_mask = pr->free_mask;
+  d.lo = pr->lo;
+  d.hi = pr->hi;
+  d.kappa = isinf(pr->C) ? 0.0 : 2.0 / pr->C;
+  d.tol_b = pp->tol_b;
+  d.tol_n = pp->tol_n;
+  d.c1 = pp->c1;
+  d.c2 = pp->c2;
+  d.max_search = pp->max_search;
+  d.max_newton = pp->max_newton;
+  d.max_ls = pp->max_ls;
+  d.search = pp->search;
+  d.ncp = pp->ncp;
+  d.stage1 = pp->stage1 ? 1 : 0;
+  for (int j = 0; j < pr->m; ++j) d.b[j] = pr->b[j];
+
+  // segments
+  if (pr->kind == PGDTO_INDEPENDENT) {
+    const int64_t* o = pr->block_offsets;
+    if (!o || o[0] != 0 || o[pr->m] != n) return PGDTO_ERR_ARG;
+    for (int j = 0; j < pr->m; ++j)
+      if (!(o[j + 1] > o[j])) return PGDTO_ERR_ARG;
+    d.nseg = pr->m;
+    for (int j = 0; j <= pr->m; ++j) d.off[j] = o[j];
+  } else {
+    d.nseg = 1;
+    d.off[0] = 0;
+    d.off[1] = n;
+  }
+  // tiles: size depends only on n and dtype
+  const int64_t unit = tile_unit(pr->dtype);
+  int64_t tile = (n + TARGET_TILES - 1) / TARGET_TILES;
+  tile = std::max<int64_t>(unit, (tile + unit - 1) / unit * unit);
+  d.tile_elems = tile;
+  int32_t tb = 0;
+  for (int s = 0; s < d.nseg; ++s) {
+    d.tile_base[s] = tb;
+    const int64_t astart = d.off[s] & ~(int64_t)31;
+    tb += (int32_t)((d.off[s + 1] - astart + tile - 1) / tile);
+  }
+  d.tile_base[d.nseg] = tb;
+  d.ntiles = tb;
+  if (tb > TILES_PAD) return PGDTO_ERR_ARG;
+  return PGDTO_OK;
+}
+
+int grid_for(pgdto_ctx* c, const Desc& d) {
+  const int ki = d.kind == PGDTO_COUPLED ? 1 : 0;
+  const int mi = d.kind == PGDTO_COUPLED ? d.m : 0;
+  int& cap = c->coop_cap[ki][d.dtype][mi];
+  if (cap == 0) cap = max_coresident(d.kind, d.dtype, d.m, c->device);
+  if (cap <= 0) return 0;
+  return std::max(1, std::min(d.ntiles, cap));
+}
+
+int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_pgd) {
+  d.part = c->part;
+  d.bar = c->bar;
+  d.result = result_dev;
+  d.pgd = is_pgd ? 1 : 0;
+  const int grid = grid_for(c, d);
+  if (grid <= 0) return PGDTO_ERR_HIP;
+  if (d.free_mask) {
+    if (hipMemsetAsync(d.free_mask, 0, (size_t)((d.n + 31) / 32) * 4, s) != hipSuccess) return PGDTO_ERR_HIP;
+  }
+  hipError_t e = launch_solve(d, grid, s, true);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)launch_mark_error(c->bar, result_dev, is_pgd ? 1 : 0, s);
+    return PGDTO_ERR_HIP;
+  }
+  c->last_grid = grid;
+  c->last_ntiles = d.ntiles;
+  return PGDTO_OK;
+}
+
+static int finish_blocking(pgdto_ctx* c, hipStream_t s, size_t bytes, void* out) {
+  if (hipMemcpyAsync(c->res_host, c->res_dev, bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return PGDTO_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return PGDTO_ERR_HIP;
+  memcpy(out, c->res_host, bytes);
+  return PGDTO_OK;
+}
+
+int fill_pgd(const pgdto_pgd_args* a, Desc& d) {
+  const pgdto_problem* pr = &a->proj;
+  const size_t esz = pr->dtype == PGDTO_F32 ? 4 : 8;
+  const size_t bytes = (size_t)pr->n * esz;
+  if (!a->rho || !a->grad || !a->dir || !a->g || !a->G) return PGDTO_ERR_ARG;
+  if (a->t < 0) return PGDTO_ERR_ARG;
+  if (a->t > 0 && (!a->rho_prev || !a->grad_prev)) return PGDTO_ERR_ARG;
+  if (!aligned16(a->rho) || !aligned16(a->grad) || !aligned16(a->dir)) return PGDTO_ERR_ARG;
+  if (a->t > 0 && (!aligned16(a->rho_prev) || !aligned16(a->grad_prev))) return PGDTO_ERR_ARG;
+  if (!(a->alpha_max > 0.0) || !(a->alpha_fallback > 0.0) || !(a->omega > 0.0) || !(a->eps_alpha >= 0.0))
+    return PGDTO_ERR_ARG;
+  if (a->cg_rule != PGDTO_CG_PR_PLUS && a->cg_rule != PGDTO_CG_FR && a->cg_rule != PGDTO_CG_NONE) return PGDTO_ERR_ARG;
+  const void* ins[] = {a->rho, a->grad, a->rho_prev, a->grad_prev};
+  for (const void* p : ins)
+    if (p && (overlaps(pr->x, bytes, p, bytes) || overlaps(a->dir, bytes, p, bytes))) return PGDTO_ERR_ARG;
+  if (overlaps(pr->x, bytes, a->dir, bytes)) return PGDTO_ERR_ARG;
+  double viol = 0.0;
+  for (int j = 0; j < pr->m; ++j) {
+    if (!isfinite(a->g[j]) || !isfinite(a->G[j])) return PGDTO_ERR_ARG;
+    d.b[j] = a->G[j] - a->g[j];           // b_j = G_j - g_j + a_j.rho_t (device adds a_j.rho_t)
+    viol = std::max(viol, a->g[j] - a->G[j]);
+  }
+  d.cg_rule = a->cg_rule;
+  d.zero_step = a->t == 0 ? 1 : 0;
+  d.fallback_forced = (a->t == 0 || (a->t >= a->t_warmup && viol > a->tol_viol)) ? 1 : 0;
+  d.rho = a->rho;
+  d.rho_prev = a->rho_prev;
+  d.grad = a->grad;
+  d.grad_prev = a->grad_prev;
+  d.dir = a->dir;
+  d.alpha_max = a->alpha_max;
+  d.alpha_fallback = a->alpha_fallback;
+  d.omega = a->omega;
+  d.eps_alpha = a->eps_alpha;
+  d.tol_stop = a->tol;
+  return PGDTO_OK;
+}
+
+}  // namespace pgdto
+
+static const pgdto_params* params_or_default(const pgdto_params* p, pgdto_params& tmp) {
+  if (p) return p;
+  pgdto_params_default(&tmp);
+  return &tmp;
+}
+
+extern "C" int pgdto_project_async(pgdto_ctx* c, const pgdto_problem* prob, const pgdto_params* params,
+                                   pgdto_result* result_dev, void* stream) {
+  if (!c || !prob || !result_dev) return PGDTO_ERR_ARG;
+  pgdto_params tmp;
+  const pgdto_params* pp = params_or_default(params, tmp);
+  Desc d;
+  int st = build_desc(prob, pp, true, d);
+  if (st != PGDTO_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return PGDTO_ERR_HIP;
+  return run_launch(c, d, (hipStream_t)stream, result_dev, false);
+}
+
+extern "C" int pgdto_project(pgdto_ctx* c, const pgdto_problem* prob, const pgdto_params* params,
+                             pgdto_result* out, void* stream) {
+  if (!c || !prob || !out) return PGDTO_ERR_ARG;
+  int st = pgdto_project_async(c, prob, params, (pgdto_result*)c->res_dev, stream);
+  if (st != PGDTO_OK) return st;
+  st = finish_blocking(c, (hipStream_t)stream, sizeof(pgdto_result), out);
+  if (st != PGDTO_OK) return st;
+  return out->error ? out->error : PGDTO_OK;
+}
+
+extern "C" int pgdto_pgd_step_async(pgdto_ctx* c, const pgdto_pgd_args* args, const pgdto_params* params,
+                                    pgdto_pgd_out* out_dev, void* stream) {
+  if (!c || !args || !out_dev) return PGDTO_ERR_ARG;
+  pgdto_params tmp;
+  const pgdto_params* pp = params_or_default(params, tmp);
+  Desc d;
+  pgdto_problem pr = args->proj;
+  // b is formed on the device; give the validator a finite stand-in
+  double zeros[PGDTO_MAX_BLOCKS] = {0};
+  pr.b = zeros;
+  int st = build_desc(&pr, pp, false, d);
+  if (st != PGDTO_OK) return st;
+  st = fill_pgd(args, d);
+  if (st != PGDTO_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return PGDTO_ERR_HIP;
+  return run_launch(c, d, (hipStream_t)stream, out_dev, true);
+}
+
+extern "C" int pgdto_pgd_step(pgdto_ctx* c, const pgdto_pgd_args* args, const pgdto_params* params,
+                              pgdto_pgd_out* out, void* stream) {
+  if (!c || !args || !out) return PGDTO_ERR_ARG;
+  int st = pgdto_pgd_step_async(c, args, params, (pgdto_pgd_out*)c->res_dev, stream);
+  if (st != PGDTO_OK) return st;
+  st = finish_blocking(c, (hipStream_t)stream, sizeof(pgdto_pgd_out), out);
+  if (st != PGDTO_OK) return st;
+  return out->proj.error ? out->proj.error : PGDTO_OK;
+}

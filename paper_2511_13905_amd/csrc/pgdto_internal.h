@@ -1,0 +1,68 @@
+// Internal definitions shared by the kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pgdto.h"
+
+namespace pgdto {
+
+constexpr int BLOCK = 512;                 // threads per workgroup (8 wave64)
+constexpr int NWAVE = BLOCK / 64;
+constexpr int NT = 2;                      // trial multipliers per 1-D search pass
+constexpr int TARGET_TILES = 256;          // tiles per instance (tile size follows n)
+constexpr int MAX_TILES = TARGET_TILES + PGDTO_MAX_BLOCKS + 8;
+constexpr int TILES_PAD = 384;             // stride of the partial-sum table
+constexpr int VMAX = 112;                  // partial values per tile (coupled, m = 8)
+constexpr int PART_DOUBLES = 2 * VMAX * TILES_PAD;   // double-buffered
+
+// Bounded spin of the grid barrier: about a second of waiting before the
+// workgroup gives up, flags PGDTO_ERR_TIMEOUT and leaves the kernel.
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
+
+// Everything one launch needs, passed by value as the kernel argument (the
+// multi-instance server kernel reads the same struct from device memory).
+struct Desc {
+  int32_t kind, dtype, m, nseg;
+  int64_t n, lda;
+  const void* y;
+  const void* A;
+  void* x;
+  uint32_t* free_mask;
+  double lo, hi, kappa;
+  double tol_b, tol_n, c1, c2;
+  int32_t max_search, max_newton, max_ls, search, ncp, stage1;
+  double b[PGDTO_MAX_BLOCKS];          // right-hand sides (pgd: G - g)
+  int64_t off[PGDTO_MAX_BLOCKS + 1];   // segment bounds (single/coupled: 0, n)
+  int32_t tile_base[PGDTO_MAX_BLOCKS + 1];
+  int64_t tile_elems;
+  int32_t ntiles;
+  // Algorithm 3 step (pgd != 0)
+  int32_t pgd, cg_rule, fallback_forced, zero_step;   // zero_step: t == 0
+  const void* rho;
+  const void* rho_prev;
+  const void* grad;
+  const void* grad_prev;
+  void* dir;
+  double alpha_max, alpha_fallback, omega, eps_alpha, tol_stop;
+  // workspace
+  double* part;          // [2][VMAX][TILES_PAD]
+  uint32_t* bar;         // [0] barrier arrivals, [1] exits, [2] error flag
+  void* result;          // pgdto_result (pgd: pgdto_pgd_out)
+};
+
+// Tiling: the tile size depends only on n and the dtype, so that an
+// instance's reduction order (and hence its bits) does not depend on how many
+// workgroups solve it.
+inline int64_t vec_elems(int dtype) { return dtype == PGDTO_F32 ? 4 : 2; }
+inline int64_t tile_unit(int dtype) { return (int64_t)BLOCK * vec_elems(dtype) * 2; }
+
+}  // namespace pgdto
+
+// Launchers (pgdto_kernels.hip)
+namespace pgdto {
+hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative);
+int max_coresident(int kind, int dtype, int m, int device);
+hipError_t launch_mark_error(uint32_t* bar, void* result, int is_pgd, hipStream_t stream);
+}  // namespace pgdto

@@ -1,0 +1,1492 @@
+// Projection kernels for gfx950 (CDNA4, wave64).
+//
+// One persistent cooperative launch solves a whole projection: every pass
+// streams y (and the constraint rows) once, each workgroup reduces its tiles
+// into per-tile partial sums, a grid barrier follows, and then EVERY
+// workgroup reduces the per-tile partials in the same fixed order and runs
+// the same float64 control logic (bracket update, Newton step, line search)
+// on bit-identical inputs.  All workgroups therefore agree on the next pass
+// without a second barrier and without the host.
+//
+// Paper references: x(lam) = clip(y - A^T lam) (Theorems 1/2, eq. delta_y),
+// h (eq. h), J = A D A^T + kappa I (eq. reg_jacobian), Algorithm 1 (bracket
+// search on the monotone dual function of Appendix A.1), Algorithm 2 (Stage 1
+// single-active candidates, semismooth Newton with line search, Appendix
+// A.2), Algorithm 3 (step size eq. final_alpha, direction eq. CG).
+//
+// Precision: streams are float32 or float64 in HBM; every per-element
+// operation is done in float64 (the FP64 vector rate of CDNA4 is half the
+// FP32 rate, far above what an 8 B/element stream needs), sums are float64
+// per thread, then a fixed wave/LDS tree, then a fixed-order cross-tile sum.
+
+#include "pgdto_internal.h"
+
+#include <math.h>
+
+namespace pgdto {
+
+enum Phase : int32_t {
+  PH_PGD_R = 1,   // Alg. 3 reductions (step size, direction, a.rho_t)
+  PH_ZERO = 2,    // lam = 0: h(0), slope, bracket end (pgd: also writes d_t, rho~)
+  PH_SEARCH = 3,  // 1-D bracket search pass (Alg. 1)
+  PH_STAGE1 = 4,  // coupled: lockstep single-row searches (Alg. 2 Stage 1)
+  PH_CHECK = 5,   // coupled: candidate feasibility (+ Newton evaluation at lam0)
+  PH_NEWTON = 6,  // coupled: h and J at a trial multiplier
+  PH_FINAL = 7,   // write x, residuals, free count, stop-test norms
+  PH_DONE = 8
+};
+
+enum SegState : int32_t { SEG_SEARCH = 0, SEG_DONE = 1 };
+
+// ------------------------------------------------------------------ loads
+
+template <typename T> struct VT;
+template <> struct VT<float> { static constexpr int N = 4; };
+template <> struct VT<double> { static constexpr int N = 2; };
+
+template <typename T>
+__device__ __forceinline__ void ld_vec(const T* __restrict__ p, int64_t e0, int64_t n, bool full, T* o) {
+  if (full) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(p + e0);
+      o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+    } else {
+      const double2 q = *reinterpret_cast<const double2*>(p + e0);
+      o[0] = q.x; o[1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VT<T>::N; ++k) o[k] = (e0 + k < n) ? p[e0 + k] : (T)0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void st_vec(T* __restrict__ p, int64_t e0, uint32_t mask, bool full, const T* v) {
+  if (full) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(p + e0) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      *reinterpret_cast<double2*>(p + e0) = make_double2(v[0], v[1]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VT<T>::N; ++k)
+      if (mask & (1u << k)) p[e0 + k] = v[k];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double f64(T v) { return (double)v; }
+
+__device__ __forceinline__ double clampd(double z, double lo, double hi) { return fmin(fmax(z, lo), hi); }
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduce NV per-thread values over the workgroup and store them as the
+// partials of `tile` (value-major layout).  Values whose bit is set in
+// `maxmask` are maxima, the rest sums.  Fixed order: xor butterfly inside the
+// wave, then waves 0..7 in order.
+template <int NV>
+__device__ __forceinline__ void block_to_part(const double (&acc)[NV], int nv, uint64_t maxmask,
+                                              double* red, double* pb, int tile) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (v < nv) {
+      const bool mx = v < 64 && ((maxmask >> v) & 1);
+      const double r = mx ? wave_max(acc[v]) : wave_sum(acc[v]);
+      if (lane == 0) red[w * VMAX + v] = r;
+    }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += BLOCK) {
+    const bool mx = v < 64 && ((maxmask >> v) & 1);
+    double r = red[v];
+#pragma unroll
+    for (int q = 1; q < NWAVE; ++q) r = mx ? fmax(r, red[q * VMAX + v]) : r + red[q * VMAX + v];
+    pb[v * TILES_PAD + tile] = r;
+  }
+  __syncthreads();
+}
+
+// Reduce the per-tile partials of every segment: tot[s * nv + v].  Every
+// workgroup runs this on the same data in the same order.
+__device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const int32_t* tile_base,
+                             int nseg, double* tot) {
+  const int pairs = nseg * nv;
+  int P = 64;
+  while (P > 1 && pairs * P > BLOCK) P >>= 1;
+  const int total = pairs * P;
+  for (int base = 0; base < total; base += BLOCK) {
+    const int idx = base + threadIdx.x;
+    const int pair = idx / P, g = idx % P;
+    const bool act = pair < pairs;
+    int v = 0, s = 0;
+    if (act) { s = pair / nv; v = pair % nv; }
+    const bool mx = act && v < 64 && ((maxmask >> v) & 1);
+    double r = mx ? -INFINITY : 0.0;
+    if (act) {
+      const int te = tile_base[s + 1];
+      for (int t = tile_base[s] + g; t < te; t += P) {
+        const double q = pb[v * TILES_PAD + t];
+        r = mx ? fmax(r, q) : r + q;
+      }
+    }
+    for (int o = P >> 1; o > 0; o >>= 1) {
+      const double q = __shfl_xor(r, o, 64);
+      r = mx ? fmax(r, q) : r + q;
+    }
+    if (act && g == 0) tot[s * nv + v] = r;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ grid barrier
+
+// Arrive-and-spin barrier on a monotonically increasing counter (reset by the
+// last workgroup to leave the kernel).  The spin is bounded: on expiry the
+// workgroup raises the error word and every workgroup leaves its loop.
+__device__ bool grid_barrier(uint32_t* bar, uint32_t nwg, uint32_t& target, int32_t* abort_flag) {
+  __syncthreads();
+  target += nwg;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    bool ok = true;
+    while (__hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SPIN_LIMIT ||
+          __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = false;
+        break;
+      }
+    }
+    __threadfence();
+    if (!ok) __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *abort_flag = ok ? 0 : 1;
+  }
+  __syncthreads();
+  return *abort_flag == 0;
+}
+
+// The last workgroup out resets the barrier words and reports a timeout.
+__device__ void kernel_exit(uint32_t* bar, uint32_t nwg, int32_t* err_field) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == nwg - 1) {
+      const uint32_t e = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (e != 0u && err_field) *err_field = PGDTO_ERR_TIMEOUT;
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ tile geometry
+
+struct TileGeom {
+  int seg;
+  int64_t sstart, send;   // segment bounds (valid elements)
+  int64_t ts, te;         // tile element range (ts 32-aligned)
+  int64_t p0;             // first vector slot of the tile
+  int nsweep;             // vector slots per thread (uniform over the block)
+};
+
+template <typename T>
+__device__ __forceinline__ TileGeom tile_geom(const Desc& d, int tile) {
+  constexpr int V = VT<T>::N;
+  TileGeom g;
+  int s = 0;
+  while (s + 1 < d.nseg && d.tile_base[s + 1] <= tile) ++s;
+  g.seg = s;
+  g.sstart = d.off[s];
+  g.send = d.off[s + 1];
+  const int64_t astart = g.sstart & ~(int64_t)31;      // 32-element aligned (free-mask words)
+  const int64_t ts = astart + (int64_t)(tile - d.tile_base[s]) * d.tile_elems;
+  const int64_t te = min(ts + d.tile_elems, g.send);
+  g.ts = ts;
+  g.te = te;
+  g.p0 = ts / V;
+  const int64_t nslots = (te - ts + V - 1) / V;
+  g.nsweep = (int)((nslots + BLOCK - 1) / BLOCK);
+  return g;
+}
+
+// For slot index k of this thread: element base e0, whether the whole vector
+// is valid, and the validity mask.
+template <typename T>
+__device__ __forceinline__ bool slot(const TileGeom& g, int k, int64_t& e0, bool& full, uint32_t& mask) {
+  constexpr int V = VT<T>::N;
+  const int64_t p = g.p0 + (int64_t)k * BLOCK + threadIdx.x;
+  e0 = p * V;
+  if (e0 >= g.send) { mask = 0; full = false; return false; }
+  full = (e0 >= g.sstart) && (e0 + V <= g.send);
+  mask = 0;
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+    if (e0 + q >= g.sstart && e0 + q < g.send) mask |= 1u << q;
+  return mask != 0;
+}
+
+// ------------------------------------------------------------------ 1-D search control
+
+// Per-row bracket state of a 1-D search on phi(lam) = a.x(lam) - b - kappa lam
+// (nonincreasing, piecewise linear; Appendix A.1).  lo < root < hi, with
+// f = phi at the ends and s = -phi' (sum of a^2 over free elements + kappa).
+struct Search {
+  double lo[PGDTO_MAX_BLOCKS], hi[PGDTO_MAX_BLOCKS];
+  double flo[PGDTO_MAX_BLOCKS], fhi[PGDTO_MAX_BLOCKS];
+  double slo[PGDTO_MAX_BLOCKS], shi[PGDTO_MAX_BLOCKS];
+  double lam[PGDTO_MAX_BLOCKS], scale[PGDTO_MAX_BLOCKS], width[PGDTO_MAX_BLOCKS];
+  double ssat[PGDTO_MAX_BLOCKS];
+  double trial[PGDTO_MAX_BLOCKS][NT];
+  int32_t state[PGDTO_MAX_BLOCKS], outcome[PGDTO_MAX_BLOCKS], npass[PGDTO_MAX_BLOCKS];
+  int32_t shrunk[PGDTO_MAX_BLOCKS];
+};
+
+__device__ __forceinline__ bool inside(double v, double lo, double hi) { return v > lo && v < hi; }
+
+__device__ void search_pick(Search& S, int s, int mode) {
+  const double lo = S.lo[s], hi = S.hi[s];
+  const double mid = 0.5 * (lo + hi);
+  if (mode == PGDTO_SEARCH_BISECT) {
+    S.trial[s][0] = mid;
+    S.trial[s][1] = NAN;
+    return;
+  }
+  const double sec = lo + S.flo[s] * ((hi - lo) / (S.flo[s] - S.fhi[s]));
+  const double nlo = S.slo[s] > 0.0 ? lo + S.flo[s] / S.slo[s] : NAN;
+  const double nhi = S.shi[s] > 0.0 ? hi + S.fhi[s] / S.shi[s] : NAN;
+  double t0 = inside(nlo, lo, hi) ? nlo : (inside(sec, lo, hi) ? sec : mid);
+  double t1;
+  if (!S.shrunk[s]) t1 = mid;                          // safeguard: force a halving
+  else if (inside(nhi, lo, hi) && nhi != t0) t1 = nhi;
+  else if (inside(sec, lo, hi) && sec != t0) t1 = sec;
+  else t1 = mid;
+  if (!inside(t0, lo, hi)) t0 = mid;
+  if (t1 == t0 || !inside(t1, lo, hi)) t1 = NAN;
+  S.trial[s][0] = t0;
+  S.trial[s][1] = t1;
+}
+
+// Initialise row/block s from the lam = 0 pass.  Returns true if the search
+// must run.  f0 = phi(0); s0 = -phi'(0); bp = largest breakpoint (the end of
+// Alg. 1's bracket, -y_l); ssat = a.x over the saturated point.
+__device__ bool search_init(Search& S, int s, double f0, double s0, double bp, double ssat,
+                            double b, double kappa, double scale, int mode) {
+  S.npass[s] = 0;
+  S.width[s] = 0.0;
+  S.scale[s] = scale;
+  S.ssat[s] = ssat;
+  S.shrunk[s] = 1;
+  if (!(f0 > 0.0)) {                  // delta(0) feasible: y* = 0 (Alg. 1, first branch)
+    S.lam[s] = 0.0;
+    S.outcome[s] = PGDTO_INACTIVE;
+    S.state[s] = SEG_DONE;
+    return false;
+  }
+  if (!(bp > 0.0) || !isfinite(bp)) bp = 0.0;
+  const double fhi = ssat - b - kappa * bp;
+  if (fhi >= 0.0) {
+    // no sign change inside the bracket: every element with a_i != 0 is
+    // saturated from bp on; phi is linear there with slope -kappa.
+    if (kappa > 0.0) {
+      S.lam[s] = bp + fhi / kappa;
+      S.outcome[s] = (ssat - b > 0.0) ? PGDTO_INFEASIBLE : PGDTO_CONVERGED;
+    } else {
+      S.lam[s] = bp;
+      S.outcome[s] = (fhi > 0.0) ? PGDTO_INFEASIBLE : PGDTO_CONVERGED;
+    }
+    S.state[s] = SEG_DONE;
+    return false;
+  }
+  S.lo[s] = 0.0; S.flo[s] = f0; S.slo[s] = s0;
+  S.hi[s] = bp;  S.fhi[s] = fhi; S.shi[s] = kappa;
+  S.state[s] = SEG_SEARCH;
+  search_pick(S, s, mode);
+  return true;
+}
+
+// Update row/block s from the sums of one search pass.  fsum[t] = a.x(trial_t),
+// ssum[t] = sum over free elements of a^2 at trial_t.
+__device__ void search_update(Search& S, int s, double f0sum, double f1sum, double s0sum, double s1sum,
+                              double b, double kappa, double tol_n, double tol_b, int max_pass, int mode) {
+  const double fsum[NT] = {f0sum, f1sum};
+  const double ssum[NT] = {s0sum, s1sum};
+  const double eps = tol_n * S.scale[s];
+  const double w0 = S.hi[s] - S.lo[s];
+  double best = NAN, bestf = INFINITY;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double lt = S.trial[s][t];
+    if (!(lt == lt)) continue;
+    const double f = fsum[t] - b - kappa * lt;
+    const double sl = ssum[t] + kappa;
+    if (mode != PGDTO_SEARCH_BISECT && fabs(f) <= eps && fabs(f) < bestf) { best = lt; bestf = fabs(f); }
+    if (f > 0.0 && lt > S.lo[s]) { S.lo[s] = lt; S.flo[s] = f; S.slo[s] = sl; }
+    else if (f <= 0.0 && lt < S.hi[s]) { S.hi[s] = lt; S.fhi[s] = f; S.shi[s] = sl; }
+  }
+  S.npass[s] += 1;
+  const double lo = S.lo[s], hi = S.hi[s];
+  const double w = hi - lo;
+  S.shrunk[s] = (w <= 0.5 * w0) ? 1 : 0;
+  if (best == best) {
+    S.lam[s] = best;
+    S.width[s] = 0.0;
+    S.outcome[s] = PGDTO_CONVERGED;
+    S.state[s] = SEG_DONE;
+    return;
+  }
+  const double res = 4.0 * fmax(fabs(hi), 1e-300) * 2.220446049250313e-16;
+  const double wtol = (mode == PGDTO_SEARCH_BISECT) ? fmax(tol_b, res) : res;
+  if (w <= wtol || S.fhi[s] == 0.0 || S.npass[s] >= max_pass) {
+    // the linear interpolation of the bracket is exact when no breakpoint lies inside
+    double l = (S.fhi[s] == 0.0) ? hi : lo + S.flo[s] * (w / (S.flo[s] - S.fhi[s]));
+    if (!(l >= lo && l <= hi)) l = 0.5 * (lo + hi);
+    S.lam[s] = l;
+    S.width[s] = w;
+    S.outcome[s] = (S.npass[s] >= max_pass && w > wtol && S.fhi[s] != 0.0) ? PGDTO_MAXITER : PGDTO_CONVERGED;
+    S.state[s] = SEG_DONE;
+    return;
+  }
+  search_pick(S, s, mode);
+}
+
+// Control parameters, copied once into LDS so that no reference to the
+// kernel argument escapes into out-of-line functions (it would be copied to
+// private memory per lane).
+struct CtlParams {
+  double kappa, tol_n, tol_b, c1, c2;
+  int32_t max_newton, max_ls, max_search, ncp, search, pad;
+};
+
+__device__ __forceinline__ void load_ctl(const Desc& d, CtlParams& P) {
+  P.kappa = d.kappa; P.tol_n = d.tol_n; P.tol_b = d.tol_b; P.c1 = d.c1; P.c2 = d.c2;
+  P.max_newton = d.max_newton; P.max_ls = d.max_ls; P.max_search = d.max_search;
+  P.ncp = d.ncp; P.search = d.search; P.pad = 0;
+}
+
+__device__ __forceinline__ int severity(int o) {
+  switch (o) {
+    case PGDTO_INACTIVE: return 0;
+    case PGDTO_CONVERGED: return 1;
+    case PGDTO_INFEASIBLE: return 2;
+    case PGDTO_MAXITER: return 3;
+    default: return 4;
+  }
+}
+
+// ------------------------------------------------------------------ Alg. 3 step rule
+
+struct PgdScalars {
+  double alpha, beta;
+  int32_t used_fb;
+};
+
+// Step size of Alg. 3 (fallback at t = 0 and, after warm-up, on constraint
+// violation; otherwise eq. final_alpha with eps_alpha) and beta of eq. CG.
+// v: ss, yy, sy, gg, gdg (= grad.(grad - grad_prev)), gpgp, ginf.
+__device__ __forceinline__ void pgd_scalars(const Desc& d, const double* v, PgdScalars& o) {
+  const double ss = v[0], yy = v[1], sy = v[2], gg = v[3], gdg = v[4], gpgp = v[5], ginf = v[6];
+  const double fb = (ginf > 0.0) ? fmin(d.alpha_max, d.alpha_fallback / ginf) : d.alpha_max;
+  o.used_fb = 0;
+  if (d.fallback_forced || yy == 0.0) {
+    o.alpha = fb;
+    o.used_fb = 1;
+  } else {
+    const double lip = sqrt(ss) / sqrt(yy);
+    o.alpha = (sy > d.eps_alpha) ? fmin(fmin(ss / sy, 2.0 * lip), d.alpha_max) : fmin(lip, d.alpha_max);
+  }
+  double beta = 0.0;
+  if (!d.zero_step && d.cg_rule != PGDTO_CG_NONE && gpgp > 0.0) {
+    beta = (d.cg_rule == PGDTO_CG_FR) ? gg / gpgp : fmax(gdg / gpgp, 0.0);
+  }
+  o.beta = beta;
+}
+
+// ================================================================== 1-D kernel
+// SINGLE and INDEPENDENT: one bracket search per segment, all segments in
+// lockstep passes (Alg. 1; Sec. 2.2.2 for independent blocks).
+
+struct Sh1D {
+  double tot[PGDTO_MAX_BLOCKS * 8];
+  double red[NWAVE * VMAX];
+  double bs[PGDTO_MAX_BLOCKS];
+  double glob[8];
+  Search S;
+  PgdScalars pg;
+  int32_t phase, abort_flag, passes, pad;
+};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
+  constexpr int V = VT<T>::N;
+  __shared__ Sh1D sh;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  const double lo = d.lo, hi = d.hi, kappa = d.kappa;
+
+  if (tid == 0) {
+    sh.phase = d.pgd ? PH_PGD_R : PH_ZERO;
+    sh.abort_flag = 0;
+    sh.passes = 0;
+    sh.pg.alpha = 0.0; sh.pg.beta = 0.0; sh.pg.used_fb = 0;
+  }
+  for (int s = tid; s < d.nseg; s += BLOCK) {
+    sh.bs[s] = d.b[s];
+    sh.S.state[s] = SEG_DONE; sh.S.lam[s] = 0.0; sh.S.npass[s] = 0; sh.S.width[s] = 0.0;
+    sh.S.outcome[s] = PGDTO_INACTIVE; sh.S.scale[s] = 1.0; sh.S.ssat[s] = 0.0;
+  }
+  __syncthreads();
+
+  uint32_t target = 0;
+  int buf = 0;
+  const T* A = (const T*)d.A;
+  T* X = (T*)d.x;
+  const T* Y = d.pgd ? (const T*)d.x : (const T*)d.y;
+
+  for (;;) {
+    const int ph = sh.phase;
+    double* pb = d.part + (size_t)buf * VMAX * TILES_PAD;
+    int nv = 0;
+    uint64_t maxmask = 0;
+
+    for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
+      const TileGeom g = tile_geom<T>(d, tile);
+      const int s = g.seg;
+      if (ph == PH_PGD_R) {
+        nv = 8; maxmask = 1ull << 6;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        acc[6] = 0.0;
+        const T* R = (const T*)d.rho; const T* RP = (const T*)d.rho_prev;
+        const T* Gr = (const T*)d.grad; const T* GP = (const T*)d.grad_prev;
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T r[V], a[V], gr[V], rp[V], gp[V];
+          ld_vec<T>(R, e0, d.n, full, r);
+          ld_vec<T>(A, e0, d.n, full, a);
+          ld_vec<T>(Gr, e0, d.n, full, gr);
+          if (!d.zero_step) { ld_vec<T>(RP, e0, d.n, full, rp); ld_vec<T>(GP, e0, d.n, full, gp); }
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            if (!d.zero_step) {
+              const double sv = f64(r[q]) - f64(rp[q]), yv = f64(gr[q]) - f64(gp[q]);
+              acc[0] = fma(sv, sv, acc[0]);
+              acc[1] = fma(yv, yv, acc[1]);
+              acc[2] = fma(sv, yv, acc[2]);
+              acc[4] = fma(f64(gr[q]), yv, acc[4]);
+              acc[5] = fma(f64(gp[q]), f64(gp[q]), acc[5]);
+            }
+            acc[3] = fma(f64(gr[q]), f64(gr[q]), acc[3]);
+            acc[6] = fmax(acc[6], fabs(f64(gr[q])));
+            acc[7] = fma(f64(a[q]), f64(r[q]), acc[7]);
+          }
+        }
+        block_to_part<8>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_ZERO) {
+        nv = 6; maxmask = 1ull << 2;
+        double acc[6] = {0, 0, -INFINITY, 0, 0, 0};
+        const T* R = (const T*)d.rho; const T* Gr = (const T*)d.grad; T* D = (T*)d.dir;
+        const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T yv[V], a[V];
+          ld_vec<T>(A, e0, d.n, full, a);
+          if (d.pgd) {
+            // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t,
+            // materialized in the stream precision (it is the point projected).
+            T r[V], gr[V], dp[V];
+            ld_vec<T>(R, e0, d.n, full, r);
+            ld_vec<T>(Gr, e0, d.n, full, gr);
+            if (!d.zero_step) ld_vec<T>(D, e0, d.n, full, dp);
+            T dn[V], rt[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              const double dd = d.zero_step ? -f64(gr[q]) : fma(beta, f64(dp[q]), -f64(gr[q]));
+              dn[q] = (T)dd;
+              rt[q] = (T)fma(step, dd, f64(r[q]));
+              yv[q] = rt[q];
+            }
+            st_vec<T>(D, e0, mask, full, dn);
+            st_vec<T>(X, e0, mask, full, rt);
+          } else {
+            ld_vec<T>(Y, e0, d.n, full, yv);
+          }
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            const double y = f64(yv[q]), av = f64(a[q]);
+            const double x0 = clampd(y, lo, hi);
+            acc[0] = fma(av, x0, acc[0]);
+            if (y >= lo && y <= hi) acc[1] = fma(av, av, acc[1]);
+            if (av != 0.0) {
+              const double bp = (av > 0.0) ? (y - lo) / av : (y - hi) / av;
+              acc[2] = fmax(acc[2], bp);
+              acc[3] += (av > 0.0) ? av * lo : av * hi;
+            }
+            acc[4] += fabs(av);
+            if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
+          }
+        }
+        block_to_part<6>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_SEARCH) {
+        nv = 2 * NT; maxmask = 0;
+        if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
+        double acc[2 * NT] = {0, 0, 0, 0};
+        double lt[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) lt[t] = sh.S.trial[s][t];
+        const bool two = (lt[1] == lt[1]);
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T yv[V], a[V];
+          ld_vec<T>(Y, e0, d.n, full, yv);
+          ld_vec<T>(A, e0, d.n, full, a);
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            const double av = f64(a[q]), a2 = av * av;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              if (t == 1 && !two) break;
+              const double z = fma(-lt[t], av, f64(yv[q]));
+              acc[2 * t] = fma(av, clampd(z, lo, hi), acc[2 * t]);
+              if (z >= lo && z <= hi) acc[2 * t + 1] += a2;
+            }
+          }
+        }
+        block_to_part<2 * NT>(acc, nv, maxmask, sh.red, pb, tile);
+      } else {  // PH_FINAL
+        nv = 4; maxmask = 0;
+        double acc[4] = {0, 0, 0, 0};
+        const double lam = sh.S.lam[s];
+        const T* R = (const T*)d.rho;
+        const int lane = tid & 63;
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          const bool any = slot<T>(g, k, e0, full, mask);
+          uint32_t bits = 0;
+          if (any) {
+            T yv[V], a[V], r[V];
+            ld_vec<T>(Y, e0, d.n, full, yv);
+            ld_vec<T>(A, e0, d.n, full, a);
+            if (d.pgd) ld_vec<T>(R, e0, d.n, full, r);
+            T xo[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              const double z = fma(-lam, f64(a[q]), f64(yv[q]));
+              xo[q] = (T)clampd(z, lo, hi);
+              if (!(mask & (1u << q))) continue;
+              const double xr = (double)xo[q];
+              acc[0] = fma(f64(a[q]), xr, acc[0]);
+              if (z >= lo && z <= hi) { acc[1] += 1.0; bits |= 1u << q; }
+              if (d.pgd) {
+                const double df = xr - f64(r[q]);
+                acc[2] = fma(df, df, acc[2]);
+                acc[3] = fma(xr, xr, acc[3]);
+              }
+            }
+            st_vec<T>(X, e0, mask, full, xo);
+          }
+          if (d.free_mask) {
+            // 32 / V lanes form one 32-bit word; OR their bits together.
+            constexpr int LPW = 32 / V;
+            uint32_t w = any ? (bits << (uint32_t)((e0 & 31))) : 0u;
+#pragma unroll
+            for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
+            if (any && (lane % LPW) == 0) {
+              const int64_t wi = e0 >> 5;
+              const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
+              if (whole) d.free_mask[wi] = w;
+              else atomicOr(&d.free_mask[wi], w);
+            }
+          }
+        }
+        block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
+      }
+    }
+    if (ph == PH_PGD_R) { nv = 8; maxmask = 1ull << 6; }
+    else if (ph == PH_ZERO) { nv = 6; maxmask = 1ull << 2; }
+    else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
+    else { nv = 4; maxmask = 0; }
+
+    if (!grid_barrier(d.bar, (uint32_t)G, target, &sh.abort_flag)) break;
+    reduce_tiles(pb, nv, maxmask, d.tile_base, d.nseg, sh.tot);
+
+    // ---------------- control (identical in every workgroup)
+    if (ph == PH_PGD_R) {
+      if (tid == 0) {
+        double v[7] = {0, 0, 0, 0, 0, 0, -INFINITY};
+        for (int s = 0; s < d.nseg; ++s) {
+          for (int q = 0; q < 6; ++q) v[q] += sh.tot[s * 8 + q];
+          v[6] = fmax(v[6], sh.tot[s * 8 + 6]);
+        }
+        pgd_scalars(d, v, sh.pg);
+        sh.passes += 1;
+      }
+      for (int s = tid; s < d.nseg; s += BLOCK) sh.bs[s] = d.b[s] + sh.tot[s * 8 + 7];
+      __syncthreads();
+      if (tid == 0) sh.phase = PH_ZERO;
+    } else if (ph == PH_ZERO) {
+      for (int s = tid; s < d.nseg; s += BLOCK) {
+        const double* t = &sh.tot[s * 6];
+        double scale = t[4] * fmax(fabs(lo), fabs(hi));
+        if (!(scale > 0.0)) scale = 1.0;
+        if (t[5] > 0.0) {
+          sh.S.lam[s] = 0.0; sh.S.outcome[s] = PGDTO_NONFINITE; sh.S.state[s] = SEG_DONE;
+          sh.S.npass[s] = 0; sh.S.width[s] = 0.0; sh.S.scale[s] = scale;
+        } else {
+          search_init(sh.S, s, t[0] - sh.bs[s], t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        sh.passes += 1;
+        int any = 0;
+        for (int s = 0; s < d.nseg; ++s) any |= (sh.S.state[s] == SEG_SEARCH);
+        sh.phase = any ? PH_SEARCH : PH_FINAL;
+      }
+    } else if (ph == PH_SEARCH) {
+      for (int s = tid; s < d.nseg; s += BLOCK) {
+        if (sh.S.state[s] != SEG_SEARCH) continue;
+        search_update(sh.S, s, sh.tot[s * 4 + 0], sh.tot[s * 4 + 2], sh.tot[s * 4 + 1], sh.tot[s * 4 + 3],
+                      sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        sh.passes += 1;
+        int any = 0;
+        for (int s = 0; s < d.nseg; ++s) any |= (sh.S.state[s] == SEG_SEARCH);
+        sh.phase = any ? PH_SEARCH : PH_FINAL;
+      }
+    } else {  // PH_FINAL: results (workgroup 0 writes)
+      if (blockIdx.x == 0) {
+        pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
+        for (int s = tid; s < d.nseg; s += BLOCK) {
+          R->lambda[s] = sh.S.lam[s];
+          R->resid[s] = sh.tot[s * 4 + 0] - sh.bs[s];
+          R->slack[s] = kappa * sh.S.lam[s];
+          R->row_outcome[s] = sh.S.outcome[s];
+        }
+        if (tid == 0) {
+          int worst = PGDTO_INACTIVE, anyact = 0, np = 0;
+          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0;
+          for (int s = 0; s < d.nseg; ++s) {
+            if (severity(sh.S.outcome[s]) > severity(worst)) worst = sh.S.outcome[s];
+            anyact |= (sh.S.outcome[s] != PGDTO_INACTIVE);
+            np = max(np, sh.S.npass[s]);
+            wmax = fmax(wmax, sh.S.width[s]);
+            nfree += sh.tot[s * 4 + 1];
+            diff2 += sh.tot[s * 4 + 2];
+            xx += sh.tot[s * 4 + 3];
+          }
+          R->outcome = worst;
+          R->error = 0;
+          R->path = anyact ? 1 : 0;
+          R->passes = sh.passes + 1;
+          R->iters_search = np;
+          R->iters_newton = 0;
+          R->iters_ls = 0;
+          R->m = d.nseg;
+          R->n_free = (int64_t)nfree;
+          R->res_inf = 0.0;
+          R->lambda_width = wmax;
+          if (d.pgd) {
+            pgdto_pgd_out* P = (pgdto_pgd_out*)d.result;
+            P->alpha = sh.pg.alpha;
+            P->beta = sh.pg.beta;
+            P->used_fallback = sh.pg.used_fb;
+            P->rel_change = (xx > 0.0) ? sqrt(diff2) / sqrt(xx) : INFINITY;
+            P->converged = (P->rel_change <= d.tol_stop) ? 1 : 0;
+          }
+        }
+      }
+      if (tid == 0) sh.phase = PH_DONE;
+    }
+    __syncthreads();
+    buf ^= 1;
+    if (sh.phase == PH_DONE) break;
+  }
+  int32_t* errp = nullptr;
+  if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
+  kernel_exit(d.bar, (uint32_t)G, errp);
+}
+
+// ================================================================== coupled kernel
+// Algorithm 2: Stage 1 (m lockstep single-row searches of the regularized
+// 1-row problem, then one pass checking every candidate lam_j* e_j against
+// all rows), Stage 2 (semismooth Newton on the m duals with the Jacobian
+// A D A^T + kappa I of eq. reg_jacobian and a line search on M = |Phi|^2/2).
+
+template <int M> struct CN {
+  static constexpr int NJ = M * (M + 1) / 2;
+  static constexpr bool FUSE = (M <= 3);
+  static constexpr int NV_R = 7 + M;
+  static constexpr int NV_ZERO = 5 * M + 1;
+  static constexpr int NV_S1 = 2 * NT * M;
+  static constexpr int NV_NEWTON = M + NJ;
+  static constexpr int NV_CHECK = M * M + (FUSE ? NV_NEWTON : 0);
+  static constexpr int NV_FINAL = M + 3;
+  static constexpr int NVM = NV_CHECK > NV_ZERO ? (NV_CHECK > NV_S1 ? NV_CHECK : NV_S1) : (NV_ZERO > NV_S1 ? NV_ZERO : NV_S1);
+};
+
+struct NewtonState {
+  double lam[PGDTO_MAX_M], h[PGDTO_MAX_M], J[PGDTO_MAX_M * PGDTO_MAX_M];   // current iterate
+  double delta[PGDTO_MAX_M], phi2, M0;                                    // direction, |Phi|^2, merit
+  double trial[PGDTO_MAX_M], gamma;
+  double blam[PGDTO_MAX_M], bh[PGDTO_MAX_M], bJ[PGDTO_MAX_M * PGDTO_MAX_M];  // best Armijo trial
+  int32_t have_best, ls, it, init;   // init: next Newton pass is the starting evaluation
+  double ht[PGDTO_MAX_M], Jt[PGDTO_MAX_M * PGDTO_MAX_M];   // evaluation from the last pass
+  double lam1[PGDTO_MAX_M];          // Stage-1 candidates
+  double h0[PGDTO_MAX_M];
+};
+
+struct ShC {
+  double tot[VMAX];
+  double red[NWAVE * VMAX];
+  double bs[PGDTO_MAX_M];
+  Search S;
+  NewtonState N;
+  PgdScalars pg;
+  CtlParams P;
+  double lamf[PGDTO_MAX_M];    // multiplier used by the final pass
+  double res_inf;
+  int32_t phase, abort_flag, passes, path, outcome, nonfinite, s1passes, pad;
+};
+
+// Unpack the symmetric Jacobian sums (upper triangle, row-major) into J[j][k].
+template <int M>
+__device__ __forceinline__ void unpack_J(const double* src, double* J) {
+  int q = 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int k = j; k < M; ++k) { J[j * PGDTO_MAX_M + k] = src[q]; J[k * PGDTO_MAX_M + j] = src[q]; ++q; }
+}
+
+// Continuous NCP: Phi_j = max(h_j, -c_j lam_j), c_j = J_jj + kappa, active if
+// h_j + c_j lam_j > 0.  Paper NCP (eq. phi): active if h_j > 0, Phi_j = h_j;
+// else Phi_j = -lam_j if h_j < 0, 0 if h_j = 0.
+template <int M>
+__device__ __forceinline__ void ncp(const double* h, const double* J, const double* lam, double kappa,
+                                    int mode, double* phi, bool* act) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (mode == PGDTO_NCP_PAPER) {
+      act[j] = h[j] > 0.0;
+      phi[j] = act[j] ? h[j] : (h[j] < 0.0 ? -lam[j] : 0.0);
+    } else {
+      const double c = J[j * PGDTO_MAX_M + j] + kappa;
+      act[j] = h[j] + c * lam[j] > 0.0;
+      phi[j] = act[j] ? h[j] : -c * lam[j];
+    }
+  }
+}
+
+// Solve the semismooth Newton system J_Phi Delta = Phi (Appendix A.2): rows
+// outside the active set release their multiplier (Delta_j = -lam_j, or 0 on
+// the paper NCP's h_j = 0 branch); active rows solve
+// (J + kappa I)_SS Delta_S = h_S - (J + kappa I)_SN Delta_N by Cholesky.
+template <int M>
+__device__ void newton_direction(const double* h, const double* J, const double* lam, double kappa,
+                                 const bool* act, const double* phi, int mode, double* delta) {
+  double K[M][M], r[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) delta[j] = act[j] ? 0.0 : (mode == PGDTO_NCP_PAPER ? phi[j] : -lam[j]);
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (act[j]) {
+      double rj = h[j];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double Jjk = J[j * PGDTO_MAX_M + k] + (j == k ? kappa : 0.0);
+        if (act[k]) K[j][k] = Jjk; else { K[j][k] = 0.0; rj -= Jjk * delta[k]; }
+      }
+      r[j] = rj;
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) K[j][k] = (j == k) ? 1.0 : 0.0;
+      r[j] = delta[j];
+    }
+  }
+  // Cholesky K = L L^T (in place, lower triangle), all indices static.
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double dj = K[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= K[j][k] * K[j][k];
+    dj = dj > 0.0 ? sqrt(dj) : sqrt(fmax(kappa, 1e-300));
+    K[j][j] = dj;
+#pragma unroll
+    for (int i = j + 1; i < M; ++i) {
+      double v = K[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= K[i][k] * K[j][k];
+      K[i][j] = v / dj;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double v = r[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) v -= K[j][k] * r[k];
+    r[j] = v / K[j][j];
+  }
+#pragma unroll
+  for (int j = M - 1; j >= 0; --j) {
+    double v = r[j];
+#pragma unroll
+    for (int k = j + 1; k < M; ++k) v -= K[k][j] * r[k];
+    r[j] = v / K[j][j];
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) if (act[j]) delta[j] = r[j];
+}
+
+// Scaled KKT residual of the current iterate (stopping rule): active rows
+// need |h_j| <= tol sigma_j, rows at lam_j = 0 need h_j <= tol sigma_j.
+template <int M>
+__device__ __forceinline__ double kkt_residual(const double* h, const double* lam, const double* scale) {
+  double r = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double v = (lam[j] > 0.0) ? fabs(h[j]) : fmax(h[j], 0.0);
+    r = fmax(r, v / scale[j]);
+  }
+  return r;
+}
+
+template <int M>
+__device__ void set_trial(NewtonState& N) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) N.trial[j] = fmax(N.lam[j] + N.gamma * N.delta[j], 0.0);
+}
+
+// Accept (lam, h, J) as the current iterate; decide to stop or start a line
+// search.  Returns the next phase.
+template <int M>
+__device__ int newton_accept(ShC& sh, const double* lam, const double* h, const double* J) {
+  NewtonState& N = sh.N;
+  const CtlParams& d = sh.P;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    N.lam[j] = lam[j];
+    N.h[j] = h[j];
+#pragma unroll
+    for (int k = 0; k < M; ++k) N.J[j * PGDTO_MAX_M + k] = J[j * PGDTO_MAX_M + k];
+  }
+  const double res = kkt_residual<M>(N.h, N.lam, sh.S.scale);
+  sh.res_inf = res;
+  if (res <= d.tol_n) {
+    sh.outcome = PGDTO_CONVERGED;
+    for (int j = 0; j < M; ++j) sh.lamf[j] = N.lam[j];
+    return PH_FINAL;
+  }
+  if (N.it >= d.max_newton) {
+    sh.outcome = PGDTO_MAXITER;
+    for (int j = 0; j < M; ++j) sh.lamf[j] = N.lam[j];
+    return PH_FINAL;
+  }
+  double phi[M];
+  bool act[M];
+  ncp<M>(N.h, N.J, N.lam, d.kappa, d.ncp, phi, act);
+  double p2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
+  N.phi2 = p2;
+  N.M0 = 0.5 * p2;
+  newton_direction<M>(N.h, N.J, N.lam, d.kappa, act, phi, d.ncp, N.delta);
+  N.gamma = 1.0;
+  N.ls = 0;
+  N.have_best = 0;
+  N.it += 1;
+  set_trial<M>(N);
+  return PH_NEWTON;
+}
+
+// Line-search decision after evaluating the trial (Appendix A.2: the
+// largest gamma in (0,1] with the Armijo condition (c1) and the curvature
+// condition (c2), searched by halving from 1).
+template <int M>
+__device__ int newton_after_trial(ShC& sh) {
+  NewtonState& N = sh.N;
+  const CtlParams& d = sh.P;
+  const double* ht = N.ht;
+  const double* Jt = N.Jt;
+  double phi[M];
+  bool act[M];
+  ncp<M>(ht, Jt, N.trial, d.kappa, d.ncp, phi, act);
+  double p2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
+  const double Mt = 0.5 * p2;
+  const bool armijo = Mt <= N.M0 - d.c1 * N.gamma * N.phi2;
+  // grad M(trial)^T Delta = Phi_t^T J_Phi(trial) Delta
+  double g = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double row;
+    if (act[j]) {
+      row = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) row += (Jt[j * PGDTO_MAX_M + k] + (j == k ? d.kappa : 0.0)) * N.delta[k];
+    } else {
+      row = (d.ncp == PGDTO_NCP_PAPER) ? N.delta[j] : (Jt[j * PGDTO_MAX_M + j] + d.kappa) * N.delta[j];
+    }
+    g += phi[j] * row;
+  }
+  const bool curv = g <= d.c2 * N.phi2;
+  N.ls += 1;
+  sh.N.init = 0;
+  if (armijo && !N.have_best) {
+    N.have_best = 1;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      N.blam[j] = N.trial[j];
+      N.bh[j] = ht[j];
+#pragma unroll
+      for (int k = 0; k < M; ++k) N.bJ[j * PGDTO_MAX_M + k] = Jt[j * PGDTO_MAX_M + k];
+    }
+  }
+  if (armijo && curv) return newton_accept<M>(sh, N.trial, ht, Jt);
+  if (N.ls >= d.max_ls) {
+    if (N.have_best) return newton_accept<M>(sh, N.blam, N.bh, N.bJ);
+    return newton_accept<M>(sh, N.trial, ht, Jt);
+  }
+  N.gamma *= 0.5;
+  set_trial<M>(N);
+  return PH_NEWTON;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
+  constexpr int V = VT<T>::N;
+  using C = CN<M>;
+  __shared__ ShC sh;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  const double lo = d.lo, hi = d.hi, kappa = d.kappa;
+
+  if (tid == 0) {
+    sh.phase = d.pgd ? PH_PGD_R : PH_ZERO;
+    sh.abort_flag = 0;
+    sh.passes = 0;
+    sh.path = 0;
+    sh.outcome = PGDTO_INACTIVE;
+    sh.nonfinite = 0;
+    sh.s1passes = 0;
+    sh.res_inf = 0.0;
+    sh.pg.alpha = 0.0; sh.pg.beta = 0.0; sh.pg.used_fb = 0;
+    sh.N.it = 0; sh.N.ls = 0; sh.N.init = 0; sh.N.have_best = 0;
+    load_ctl(d, sh.P);
+  }
+  if (tid < M) {
+    sh.bs[tid] = d.b[tid]; sh.lamf[tid] = 0.0; sh.N.lam1[tid] = 0.0;
+    sh.S.state[tid] = SEG_DONE; sh.S.lam[tid] = 0.0; sh.S.npass[tid] = 0; sh.S.width[tid] = 0.0;
+    sh.S.outcome[tid] = PGDTO_INACTIVE; sh.S.scale[tid] = 1.0; sh.S.ssat[tid] = 0.0;
+  }
+  __syncthreads();
+
+  uint32_t target = 0;
+  int buf = 0;
+  const T* Arow[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) Arow[j] = (const T*)d.A + (int64_t)j * d.lda;
+  T* X = (T*)d.x;
+  const T* Y = d.pgd ? (const T*)d.x : (const T*)d.y;
+  int ls_total = 0;
+
+  for (;;) {
+    const int ph = sh.phase;
+    double* pb = d.part + (size_t)buf * VMAX * TILES_PAD;
+    int nv;
+    uint64_t maxmask = 0;
+    switch (ph) {
+      case PH_PGD_R: nv = C::NV_R; maxmask = 1ull << 6; break;
+      case PH_ZERO: nv = C::NV_ZERO; maxmask = ((1ull << M) - 1) << (2 * M); break;
+      case PH_STAGE1: nv = C::NV_S1; break;
+      case PH_CHECK: nv = C::NV_CHECK; break;
+      case PH_NEWTON: nv = C::NV_NEWTON; break;
+      default: nv = C::NV_FINAL; break;
+    }
+
+    for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
+      const TileGeom g = tile_geom<T>(d, tile);
+      if (ph == PH_PGD_R) {
+        double acc[C::NV_R];
+#pragma unroll
+        for (int v = 0; v < C::NV_R; ++v) acc[v] = 0.0;
+        const T* R = (const T*)d.rho; const T* RP = (const T*)d.rho_prev;
+        const T* Gr = (const T*)d.grad; const T* GP = (const T*)d.grad_prev;
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T r[V], gr[V], rp[V], gp[V], a[M][V];
+          ld_vec<T>(R, e0, d.n, full, r);
+          ld_vec<T>(Gr, e0, d.n, full, gr);
+          if (!d.zero_step) { ld_vec<T>(RP, e0, d.n, full, rp); ld_vec<T>(GP, e0, d.n, full, gp); }
+#pragma unroll
+          for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            if (!d.zero_step) {
+              const double sv = f64(r[q]) - f64(rp[q]), yv = f64(gr[q]) - f64(gp[q]);
+              acc[0] = fma(sv, sv, acc[0]);
+              acc[1] = fma(yv, yv, acc[1]);
+              acc[2] = fma(sv, yv, acc[2]);
+              acc[4] = fma(f64(gr[q]), yv, acc[4]);
+              acc[5] = fma(f64(gp[q]), f64(gp[q]), acc[5]);
+            }
+            acc[3] = fma(f64(gr[q]), f64(gr[q]), acc[3]);
+            acc[6] = fmax(acc[6], fabs(f64(gr[q])));
+#pragma unroll
+            for (int j = 0; j < M; ++j) acc[7 + j] = fma(f64(a[j][q]), f64(r[q]), acc[7 + j]);
+          }
+        }
+        block_to_part<C::NV_R>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_ZERO) {
+        double acc[C::NV_ZERO];
+#pragma unroll
+        for (int v = 0; v < C::NV_ZERO; ++v) acc[v] = (v >= 2 * M && v < 3 * M) ? -INFINITY : 0.0;
+        const T* R = (const T*)d.rho; const T* Gr = (const T*)d.grad; T* D = (T*)d.dir;
+        const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T yv[V], a[M][V];
+#pragma unroll
+          for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+          if (d.pgd) {
+            T r[V], gr[V], dp[V];
+            ld_vec<T>(R, e0, d.n, full, r);
+            ld_vec<T>(Gr, e0, d.n, full, gr);
+            if (!d.zero_step) ld_vec<T>(D, e0, d.n, full, dp);
+            T dn[V], rt[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              const double dd = d.zero_step ? -f64(gr[q]) : fma(beta, f64(dp[q]), -f64(gr[q]));
+              dn[q] = (T)dd;
+              rt[q] = (T)fma(step, dd, f64(r[q]));
+              yv[q] = rt[q];
+            }
+            st_vec<T>(D, e0, mask, full, dn);
+            st_vec<T>(X, e0, mask, full, rt);
+          } else {
+            ld_vec<T>(Y, e0, d.n, full, yv);
+          }
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            const double y = f64(yv[q]);
+            const double x0 = clampd(y, lo, hi);
+            const bool fr = (y >= lo && y <= hi);
+            bool bad = !isfinite(y);
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const double av = f64(a[j][q]);
+              acc[j] = fma(av, x0, acc[j]);
+              if (fr) acc[M + j] = fma(av, av, acc[M + j]);
+              if (av != 0.0) {
+                const double bp = (av > 0.0) ? (y - lo) / av : (y - hi) / av;
+                acc[2 * M + j] = fmax(acc[2 * M + j], bp);
+                acc[3 * M + j] += (av > 0.0) ? av * lo : av * hi;
+              }
+              acc[4 * M + j] += fabs(av);
+              bad |= !isfinite(av);
+            }
+            if (bad) acc[5 * M] += 1.0;
+          }
+        }
+        block_to_part<C::NV_ZERO>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_STAGE1) {
+        double acc[C::NV_S1];
+#pragma unroll
+        for (int v = 0; v < C::NV_S1; ++v) acc[v] = 0.0;
+        double lt[M][NT];
+        bool on[M][NT];
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            lt[j][t] = sh.S.trial[j][t];
+            on[j][t] = (sh.S.state[j] == SEG_SEARCH) && (lt[j][t] == lt[j][t]);
+          }
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T yv[V], a[M][V];
+          ld_vec<T>(Y, e0, d.n, full, yv);
+#pragma unroll
+          for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const double av = f64(a[j][q]);
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+                if (!on[j][t]) continue;
+                const double z = fma(-lt[j][t], av, f64(yv[q]));
+                acc[(j * NT + t) * 2] = fma(av, clampd(z, lo, hi), acc[(j * NT + t) * 2]);
+                if (z >= lo && z <= hi) acc[(j * NT + t) * 2 + 1] = fma(av, av, acc[(j * NT + t) * 2 + 1]);
+              }
+            }
+          }
+        }
+        block_to_part<C::NV_S1>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_CHECK || ph == PH_NEWTON) {
+        // PH_NEWTON: h and the upper triangle of A D A^T at the trial point.
+        // PH_CHECK: candidate sums a_k.x(lam_j* e_j) (+ the Newton sums at lam0).
+        constexpr int NVC = C::NV_CHECK > C::NV_NEWTON ? C::NV_CHECK : C::NV_NEWTON;
+        double acc[NVC];
+#pragma unroll
+        for (int v = 0; v < NVC; ++v) acc[v] = 0.0;
+        const bool check = (ph == PH_CHECK);
+        const bool newton = (ph == PH_NEWTON) || C::FUSE;
+        const int nbase = check ? M * M : 0;
+        double lamv[M], cand[M];
+        bool con[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          lamv[j] = check ? sh.N.lam1[j] : sh.N.trial[j];
+          cand[j] = sh.N.lam1[j];
+          con[j] = check && (cand[j] > 0.0);
+        }
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          if (!slot<T>(g, k, e0, full, mask)) continue;
+          T yv[V], a[M][V];
+          ld_vec<T>(Y, e0, d.n, full, yv);
+#pragma unroll
+          for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            if (check) {
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                if (!con[j]) continue;
+                const double xc = clampd(fma(-cand[j], f64(a[j][q]), f64(yv[q])), lo, hi);
+#pragma unroll
+                for (int kk = 0; kk < M; ++kk) acc[j * M + kk] = fma(f64(a[kk][q]), xc, acc[j * M + kk]);
+              }
+            }
+            if (newton) {
+              double z = f64(yv[q]);
+#pragma unroll
+              for (int j = 0; j < M; ++j) z = fma(-lamv[j], f64(a[j][q]), z);
+              const double x = clampd(z, lo, hi);
+              const bool fr = (z >= lo && z <= hi);
+              double fa[M];
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                acc[nbase + j] = fma(f64(a[j][q]), x, acc[nbase + j]);
+                fa[j] = fr ? f64(a[j][q]) : 0.0;
+              }
+              int p = nbase + M;
+#pragma unroll
+              for (int j = 0; j < M; ++j)
+#pragma unroll
+                for (int kk = j; kk < M; ++kk) { acc[p] = fma(fa[j], f64(a[kk][q]), acc[p]); ++p; }
+            }
+          }
+        }
+        block_to_part<NVC>(acc, nv, maxmask, sh.red, pb, tile);
+      } else {  // PH_FINAL
+        double acc[C::NV_FINAL];
+#pragma unroll
+        for (int v = 0; v < C::NV_FINAL; ++v) acc[v] = 0.0;
+        double lamv[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) lamv[j] = sh.lamf[j];
+        const T* R = (const T*)d.rho;
+        const int lane = tid & 63;
+        for (int k = 0; k < g.nsweep; ++k) {
+          int64_t e0; bool full; uint32_t mask;
+          const bool any = slot<T>(g, k, e0, full, mask);
+          uint32_t bits = 0;
+          if (any) {
+            T yv[V], a[M][V], r[V];
+            ld_vec<T>(Y, e0, d.n, full, yv);
+#pragma unroll
+            for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+            if (d.pgd) ld_vec<T>(R, e0, d.n, full, r);
+            T xo[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              double z = f64(yv[q]);
+#pragma unroll
+              for (int j = 0; j < M; ++j) z = fma(-lamv[j], f64(a[j][q]), z);
+              xo[q] = (T)clampd(z, lo, hi);
+              if (!(mask & (1u << q))) continue;
+              const double xr = (double)xo[q];
+#pragma unroll
+              for (int j = 0; j < M; ++j) acc[j] = fma(f64(a[j][q]), xr, acc[j]);
+              if (z >= lo && z <= hi) { acc[M] += 1.0; bits |= 1u << q; }
+              if (d.pgd) {
+                const double df = xr - f64(r[q]);
+                acc[M + 1] = fma(df, df, acc[M + 1]);
+                acc[M + 2] = fma(xr, xr, acc[M + 2]);
+              }
+            }
+            st_vec<T>(X, e0, mask, full, xo);
+          }
+          if (d.free_mask) {
+            constexpr int LPW = 32 / V;
+            uint32_t w = any ? (bits << (uint32_t)(e0 & 31)) : 0u;
+#pragma unroll
+            for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
+            if (any && (lane % LPW) == 0) {
+              const int64_t wi = e0 >> 5;
+              const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
+              if (whole) d.free_mask[wi] = w;
+              else atomicOr(&d.free_mask[wi], w);
+            }
+          }
+        }
+        block_to_part<C::NV_FINAL>(acc, nv, maxmask, sh.red, pb, tile);
+      }
+    }
+
+    if (!grid_barrier(d.bar, (uint32_t)G, target, &sh.abort_flag)) break;
+    reduce_tiles(pb, nv, maxmask, d.tile_base, 1, sh.tot);
+
+    // ---------------- control (identical in every workgroup)
+    const double* t = sh.tot;
+    if (ph == PH_PGD_R) {
+      if (tid == 0) {
+        pgd_scalars(d, t, sh.pg);
+        sh.passes += 1;
+        for (int j = 0; j < M; ++j) sh.bs[j] = d.b[j] + t[7 + j];
+        sh.phase = PH_ZERO;
+      }
+    } else if (ph == PH_ZERO) {
+      if (tid < M) {
+        const int j = tid;
+        double scale = t[4 * M + j] * fmax(fabs(lo), fabs(hi));
+        if (!(scale > 0.0)) scale = 1.0;
+        sh.S.scale[j] = scale;
+        sh.N.h0[j] = t[j] - sh.bs[j];
+        sh.S.ssat[j] = t[3 * M + j];
+        if (d.stage1 && t[5 * M] == 0.0) {
+          search_init(sh.S, j, t[j] - sh.bs[j], t[M + j] + kappa, t[2 * M + j], t[3 * M + j], sh.bs[j], kappa,
+                      scale, d.search);
+        } else {
+          sh.S.state[j] = SEG_DONE; sh.S.lam[j] = 0.0; sh.S.npass[j] = 0;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        sh.passes += 1;
+        bool any_pos = false;
+        for (int j = 0; j < M; ++j) any_pos |= (sh.N.h0[j] > 0.0);
+        if (t[5 * M] > 0.0) {
+          sh.nonfinite = 1;
+          sh.outcome = PGDTO_NONFINITE;
+          sh.phase = PH_FINAL;
+        } else if (!any_pos) {
+          sh.outcome = PGDTO_INACTIVE;
+          sh.path = 0;
+          sh.phase = PH_FINAL;
+        } else if (!d.stage1) {
+          sh.path = 3;
+          for (int j = 0; j < M; ++j) sh.N.trial[j] = 0.0;
+          sh.N.init = 1;
+          sh.phase = PH_NEWTON;
+        } else {
+          int any = 0;
+          for (int j = 0; j < M; ++j) any |= (sh.S.state[j] == SEG_SEARCH);
+          sh.phase = any ? PH_STAGE1 : PH_CHECK;
+          if (!any) for (int j = 0; j < M; ++j) sh.N.lam1[j] = sh.S.lam[j];
+        }
+      }
+    } else if (ph == PH_STAGE1) {
+      if (tid < M && sh.S.state[tid] == SEG_SEARCH) {
+        const int j = tid;
+        search_update(sh.S, j, t[(j * NT + 0) * 2], t[(j * NT + 1) * 2], t[(j * NT + 0) * 2 + 1],
+                      t[(j * NT + 1) * 2 + 1], sh.bs[j], kappa, d.tol_n, d.tol_b, d.max_search, d.search);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        sh.passes += 1;
+        sh.s1passes += 1;
+        int any = 0;
+        for (int j = 0; j < M; ++j) any |= (sh.S.state[j] == SEG_SEARCH);
+        if (!any) {
+          for (int j = 0; j < M; ++j) sh.N.lam1[j] = sh.S.lam[j];
+          sh.phase = PH_CHECK;
+        }
+      }
+    } else if (ph == PH_CHECK) {
+      if (tid == 0) {
+        sh.passes += 1;
+        int found = -1;
+        for (int j = 0; j < M && found < 0; ++j) {
+          if (!(sh.N.lam1[j] > 0.0)) continue;
+          bool ok = true;
+          for (int k = 0; k < M; ++k) {
+            const double hk = t[j * M + k] - sh.bs[k] - (k == j ? kappa * sh.N.lam1[j] : 0.0);
+            if (hk > d.tol_n * sh.S.scale[k]) { ok = false; break; }
+          }
+          if (ok) found = j;
+        }
+        if (found >= 0) {
+          for (int j = 0; j < M; ++j) sh.lamf[j] = (j == found) ? sh.N.lam1[j] : 0.0;
+          sh.path = 2;
+          sh.outcome = PGDTO_CONVERGED;
+          sh.phase = PH_FINAL;
+        } else {
+          sh.path = 3;
+          if (C::FUSE) {
+            for (int j = 0; j < M; ++j) sh.N.ht[j] = t[M * M + j] - sh.bs[j] - kappa * sh.N.lam1[j];
+            unpack_J<M>(&t[M * M + M], sh.N.Jt);
+            sh.phase = newton_accept<M>(sh, sh.N.lam1, sh.N.ht, sh.N.Jt);
+          } else {
+            for (int j = 0; j < M; ++j) sh.N.trial[j] = sh.N.lam1[j];
+            sh.N.init = 1;
+            sh.phase = PH_NEWTON;
+          }
+        }
+      }
+    } else if (ph == PH_NEWTON) {
+      if (tid == 0) {
+        sh.passes += 1;
+        ls_total += 1;
+        for (int j = 0; j < M; ++j) sh.N.ht[j] = t[j] - sh.bs[j] - kappa * sh.N.trial[j];
+        unpack_J<M>(&t[M], sh.N.Jt);
+        if (sh.N.init) {
+          sh.N.init = 0;
+          sh.phase = newton_accept<M>(sh, sh.N.trial, sh.N.ht, sh.N.Jt);
+        } else {
+          sh.phase = newton_after_trial<M>(sh);
+        }
+      }
+    } else {  // PH_FINAL
+      if (blockIdx.x == 0) {
+        pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
+        if (tid < M) {
+          const int j = tid;
+          R->lambda[j] = sh.lamf[j];
+          R->resid[j] = t[j] - sh.bs[j];
+          R->slack[j] = kappa * sh.lamf[j];
+          int o = sh.lamf[j] > 0.0 ? PGDTO_CONVERGED : PGDTO_INACTIVE;
+          if (sh.S.ssat[j] - sh.bs[j] > 0.0) o = PGDTO_INFEASIBLE;
+          if (sh.outcome == PGDTO_MAXITER || sh.outcome == PGDTO_NONFINITE) o = sh.outcome;
+          R->row_outcome[j] = o;
+        }
+        if (tid == 0) {
+          int worst = sh.outcome;
+          for (int j = 0; j < M; ++j)
+            if (sh.S.ssat[j] - sh.bs[j] > 0.0 && severity(PGDTO_INFEASIBLE) > severity(worst)) worst = PGDTO_INFEASIBLE;
+          R->outcome = worst;
+          R->error = 0;
+          R->path = sh.path;
+          R->passes = sh.passes + 1;
+          int np = 0;
+          for (int j = 0; j < M; ++j) np = max(np, sh.S.npass[j]);
+          R->iters_search = np;
+          R->iters_newton = sh.N.it;
+          R->iters_ls = ls_total;
+          R->m = M;
+          R->n_free = (int64_t)t[M];
+          R->res_inf = sh.res_inf;
+          double wmax = 0.0;
+          for (int j = 0; j < M; ++j) wmax = fmax(wmax, sh.S.width[j]);
+          R->lambda_width = wmax;
+          if (d.pgd) {
+            pgdto_pgd_out* P = (pgdto_pgd_out*)d.result;
+            P->alpha = sh.pg.alpha;
+            P->beta = sh.pg.beta;
+            P->used_fallback = sh.pg.used_fb;
+            P->rel_change = (t[M + 2] > 0.0) ? sqrt(t[M + 1]) / sqrt(t[M + 2]) : INFINITY;
+            P->converged = (P->rel_change <= d.tol_stop) ? 1 : 0;
+          }
+        }
+      }
+      if (tid == 0) sh.phase = PH_DONE;
+    }
+    __syncthreads();
+    buf ^= 1;
+    if (sh.phase == PH_DONE) break;
+  }
+  int32_t* errp = nullptr;
+  if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
+  kernel_exit(d.bar, (uint32_t)G, errp);
+}
+
+// Marks a result as failed and clears the barrier words (used by the host
+// after a failed launch).
+__global__ void k_mark_error(uint32_t* bar, void* result, int is_pgd) {
+  if (threadIdx.x == 0) {
+    bar[0] = 0; bar[1] = 0; bar[2] = 0;
+    if (result) {
+      pgdto_result* R = is_pgd ? &((pgdto_pgd_out*)result)->proj : (pgdto_result*)result;
+      R->error = PGDTO_ERR_HIP;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T>
+static const void* coupled_fn(int m) {
+  switch (m) {
+    case 1: return (const void*)k_solve_coupled<T, 1>;
+    case 2: return (const void*)k_solve_coupled<T, 2>;
+    case 3: return (const void*)k_solve_coupled<T, 3>;
+    case 4: return (const void*)k_solve_coupled<T, 4>;
+    case 5: return (const void*)k_solve_coupled<T, 5>;
+    case 6: return (const void*)k_solve_coupled<T, 6>;
+    case 7: return (const void*)k_solve_coupled<T, 7>;
+    default: return (const void*)k_solve_coupled<T, 8>;
+  }
+}
+
+static const void* kernel_fn(int kind, int dtype, int m) {
+  if (kind == PGDTO_COUPLED) return dtype == PGDTO_F32 ? coupled_fn<float>(m) : coupled_fn<double>(m);
+  return dtype == PGDTO_F32 ? (const void*)k_solve_1d<float> : (const void*)k_solve_1d<double>;
+}
+
+int max_coresident(int kind, int dtype, int m, int device) {
+  int nb = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_fn(kind, dtype, m), BLOCK, 0) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return nb * ncu;
+}
+
+hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative) {
+  Desc copy = d;
+  void* args[] = {&copy};
+  const void* fn = kernel_fn(d.kind, d.dtype, d.m);
+  if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
+  return hipLaunchKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
+}
+
+hipError_t launch_mark_error(uint32_t* bar, void* result, int is_pgd, hipStream_t stream) {
+  hipLaunchKernelGGL(k_mark_error, dim3(1), dim3(64), 0, stream, bar, result, is_pgd);
+  return hipGetLastError();
+}
+
+}  // namespace pgdto

@@ -1,0 +1,241 @@
+// Batch / serving front end of the C ABI.
+//
+// Requests are queued on submit and retired through poll/wait.  Admission
+// keeps the summed footprint (y, A, x bytes) of the requests in flight under
+// the configured HBM budget.  This file holds the request bookkeeping and the
+// one-at-a-time executor; the slot-based persistent executor lives in
+// pgdto_server.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pgdto_ctx.h"
+#include "pgdto_internal.h"
+#include "pgdto_serve.h"
+
+namespace pgdto {
+
+size_t request_footprint(const pgdto_problem& p) {
+  const size_t esz = p.dtype == PGDTO_F32 ? 4 : 8;
+  const size_t n = (size_t)p.n;
+  const size_t rows = p.kind == PGDTO_INDEPENDENT ? 1 : (size_t)p.m;
+  return esz * n * (rows + 2);
+}
+
+}  // namespace pgdto
+
+using namespace pgdto;
+
+extern "C" int pgdto_batch_create(pgdto_ctx* ctx, const pgdto_batch_cfg* cfg, pgdto_batch** out) {
+  if (!ctx || !out) return PGDTO_ERR_ARG;
+  *out = nullptr;
+  pgdto_batch_cfg c{};
+  if (cfg) c = *cfg;
+  if (c.max_slots < 0 || c.wg_per_slot < 0 || c.queue_capacity < 0) return PGDTO_ERR_ARG;
+  if (c.queue_capacity == 0) c.queue_capacity = 65536;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PGDTO_ERR_HIP;
+  if (c.hbm_budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return PGDTO_ERR_HIP;
+    c.hbm_budget_bytes = (size_t)(0.9 * (double)fr);
+  }
+  pgdto_batch* b = new (std::nothrow) pgdto_batch();
+  if (!b) return PGDTO_ERR_NOMEM;
+  b->ctx = ctx;
+  b->cfg = c;
+  int st = b->start();
+  if (st != PGDTO_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return PGDTO_OK;
+}
+
+extern "C" int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, const pgdto_params* params,
+                                  uint64_t* ticket) {
+  if (!b || !prob || !ticket) return PGDTO_ERR_ARG;
+  pgdto_params pp;
+  if (params) pp = *params; else pgdto_params_default(&pp);
+  // validate now (host only) so that a bad request fails at submit
+  Desc d;
+  int st = build_desc(prob, &pp, true, d);
+  if (st != PGDTO_OK) return st;
+  Request r;
+  r.prob = *prob;
+  r.params = pp;
+  r.m = prob->m;
+  for (int j = 0; j < prob->m; ++j) r.b[j] = prob->b[j];
+  if (prob->kind == PGDTO_INDEPENDENT)
+    for (int j = 0; j <= prob->m; ++j) r.off[j] = prob->block_offsets[j];
+  r.prob.b = nullptr;
+  r.prob.block_offsets = nullptr;
+  r.footprint = request_footprint(*prob);
+  if (r.footprint > b->cfg.hbm_budget_bytes) return PGDTO_ERR_NOMEM;
+  return b->submit(r, ticket);
+}
+
+extern "C" int pgdto_batch_poll(pgdto_batch* b, uint64_t ticket, pgdto_result* out) {
+  if (!b || !out) return PGDTO_ERR_ARG;
+  return b->poll(ticket, out, false);
+}
+
+extern "C" int pgdto_batch_wait(pgdto_batch* b, uint64_t ticket, pgdto_result* out) {
+  if (!b || !out) return PGDTO_ERR_ARG;
+  return b->poll(ticket, out, true);
+}
+
+extern "C" int pgdto_batch_stats(pgdto_batch* b, int64_t* admitted, int64_t* completed, int64_t* queued,
+                                 int64_t* in_flight, int64_t* peak_bytes) {
+  if (!b) return PGDTO_ERR_ARG;
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (admitted) *admitted = b->n_admitted;
+  if (completed) *completed = b->n_completed;
+  if (queued) *queued = (int64_t)b->queue.size();
+  if (in_flight) *in_flight = b->n_in_flight;
+  if (peak_bytes) *peak_bytes = (int64_t)b->peak_bytes;
+  return PGDTO_OK;
+}
+
+extern "C" int pgdto_batch_destroy(pgdto_batch* b) {
+  if (!b) return PGDTO_ERR_ARG;
+  b->stop();
+  delete b;
+  return PGDTO_OK;
+}
+
+// ------------------------------------------------------------------ pgdto_batch
+
+int pgdto_batch::submit(const Request& r0, uint64_t* ticket) {
+  std::lock_guard<std::mutex> lk(mu);
+  if (stopping) return PGDTO_ERR_CANCELLED;
+  if ((int)queue.size() >= cfg.queue_capacity) return PGDTO_ERR_BUSY;
+  Request r = r0;
+  r.ticket = next_ticket++;
+  r.state = PGDTO_QUEUED;
+  records[r.ticket] = Record{PGDTO_QUEUED, {}};
+  queue.push_back(r);
+  *ticket = r.ticket;
+  cv.notify_all();
+  return PGDTO_OK;
+}
+
+int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait) {
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    auto it = records.find(ticket);
+    if (it == records.end()) return PGDTO_ERR_UNKNOWN_TICKET;
+    const int st = it->second.state;
+    if (st == PGDTO_OK || st < 0) {
+      *out = it->second.result;
+      records.erase(it);
+      return st;
+    }
+    if (!wait) return st;
+    done_cv.wait(lk);
+  }
+}
+
+void pgdto_batch::finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint) {
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = records.find(ticket);
+  if (it != records.end()) {
+    it->second.state = status;
+    it->second.result = res;
+  }
+  n_completed += 1;
+  n_in_flight -= 1;
+  bytes_in_flight -= footprint;
+  done_cv.notify_all();
+  cv.notify_all();
+}
+
+// Admits the next request if the budget and a free executor allow it.
+bool pgdto_batch::pop_admissible(Request& r, size_t slots_free) {
+  if (queue.empty() || slots_free == 0) return false;
+  const Request& h = queue.front();
+  if (bytes_in_flight + h.footprint > cfg.hbm_budget_bytes && n_in_flight > 0) return false;
+  r = h;
+  queue.pop_front();
+  bytes_in_flight += r.footprint;
+  peak_bytes = std::max(peak_bytes, bytes_in_flight);
+  n_in_flight += 1;
+  n_admitted += 1;
+  auto it = records.find(r.ticket);
+  if (it != records.end()) it->second.state = PGDTO_PENDING;
+  return true;
+}
+
+void pgdto_batch::cancel_queued() {
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& r : queue) {
+    auto it = records.find(r.ticket);
+    if (it != records.end()) {
+      it->second.state = PGDTO_ERR_CANCELLED;
+      memset(&it->second.result, 0, sizeof(pgdto_result));
+    }
+  }
+  queue.clear();
+  done_cv.notify_all();
+}
+
+// One-at-a-time executor: the plain per-request path (FIFO, eager launches).
+void pgdto_batch::run_plain() {
+  (void)hipSetDevice(ctx->device);
+  for (;;) {
+    Request r;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stopping || !queue.empty(); });
+      if (stopping && queue.empty()) return;
+      if (!pop_admissible(r, 1)) continue;
+    }
+    pgdto_problem p = r.prob;
+    p.b = r.b;
+    p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
+    pgdto_result res;
+    memset(&res, 0, sizeof(res));
+    int st = pgdto_project(plain_ctx, &p, &r.params, &res, (void*)plain_stream);
+    finish(r.ticket, st, res, r.footprint);
+  }
+}
+
+int pgdto_batch::start() {
+  if (hipStreamCreateWithFlags(&plain_stream, hipStreamNonBlocking) != hipSuccess) return PGDTO_ERR_HIP;
+  int st = pgdto_ctx_create(ctx->device, &plain_ctx);
+  if (st != PGDTO_OK) return st;
+  if (cfg.max_slots > 1 || cfg.max_slots == 0) {
+    st = server_start(this);
+    if (st != PGDTO_OK) return st;
+  } else {
+    worker = std::thread([this] { run_plain(); });
+  }
+  return PGDTO_OK;
+}
+
+void pgdto_batch::stop() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stopping = true;
+    cv.notify_all();
+  }
+  if (server) {
+    // in-flight requests finish; queued ones are cancelled
+    cancel_queued();
+    server_stop(this);
+  }
+  if (worker.joinable()) worker.join();
+  cancel_queued();
+  if (plain_ctx) pgdto_ctx_destroy(plain_ctx);
+  if (plain_stream) (void)hipStreamDestroy(plain_stream);
+}

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP projection (through the C ABI) against the CPU oracle.
+
+Every case prints its name, seed and shape before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import projection as P
+from paper_2511_13905_amd import inputs as I
+
+from parity import check, free_from_mask
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2511_13905_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def run(ctx, p, params=None, want_mask=True):
+    y = dev(p.y)
+    A = dev(p.A)
+    mask = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0") if want_mask else None
+    x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=mask, params=params)
+    torch.cuda.synchronize()
+    xm = x.cpu().numpy()
+    fm = free_from_mask(mask.cpu().numpy().view(np.uint32), p.n) if want_mask else None
+    return xm, r, fm
+
+
+def orc(p):
+    return oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets)
+
+
+# ------------------------------------------------------------------ single row
+
+@pytest.mark.parametrize("seed", range(12))
+def test_volume_2d_f64(ctx, seed):
+    p = I.volume_2d(seed, vf=0.5)
+    say("volume_2d f64", seed, p.n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+    assert r["outcome"] == ref.outcome[0]
+    if ref.outcome[0] == "inactive":
+        np.testing.assert_array_equal(x, np.clip(p.y, p.lo, p.hi))
+    else:
+        assert r["lam"][0] == pytest.approx(ref.lam[0], rel=1e-9)
+
+
+@pytest.mark.parametrize("n", [1, 3, 5, 1000, 4097, 65537, 200003])
+def test_compliance_ragged_f32(ctx, n):
+    p = I.compliance_3d(n % 7, n=n)
+    say("compliance f32 ragged", n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+    assert r["outcome"] == ref.outcome[0]
+    assert r["lam"][0] == pytest.approx(ref.lam[0], rel=1e-9, abs=1e-12)
+
+
+def test_compliance_full_size(ctx):
+    p = I.compliance_3d(0)
+    say("compliance f32 full", p.n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    info = check(p, x, r, ref, fm)
+    assert r["lam"][0] == pytest.approx(ref.lam[0], rel=1e-9)
+    assert r["passes"] <= 16
+    print("passes", r["passes"], info, flush=True)
+
+
+def test_compliance_f64(ctx):
+    p = I.compliance_3d(5, n=300001, dtype=np.float64)
+    say("compliance f64", p.n)
+    x, r, fm = run(ctx, p)
+    check(p, x, r, orc(p), fm)
+
+
+# ------------------------------------------------------------------ independent blocks
+
+@pytest.mark.parametrize("n_per", [1, 7, 30001, 131072])
+def test_multimaterial(ctx, n_per):
+    p = I.multi_material(n_per % 5, fields=4, n_per=n_per)
+    say("multimaterial", n_per)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+    for j in range(4):
+        assert r["row_outcome"][j] == ref.outcome[j]
+        assert r["lam"][j] == pytest.approx(ref.lam[j], rel=1e-9, abs=1e-9)
+
+
+def test_multimaterial_full_size(ctx):
+    p = I.multi_material(0)
+    say("multimaterial full", p.n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+
+
+def test_many_uneven_blocks(ctx):
+    """64 blocks (the maximum) of uneven, unaligned sizes; mixed active/inactive."""
+    rng = np.random.default_rng(44)
+    sizes = rng.integers(1, 9000, 64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    y = rng.uniform(-0.3, 1.3, n).astype(np.float32)
+    c = (1.0 / np.repeat(sizes, sizes)).astype(np.float32)
+    caps = rng.uniform(0.1, 0.8, 64)
+    p = I.Problem("independent", y, c, caps, offsets=off)
+    say("many blocks", n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+    assert [o for o in r["row_outcome"]] == ref.outcome
+
+
+# ------------------------------------------------------------------ coupled rows
+
+@pytest.mark.parametrize("seed", range(6))
+def test_volume_com_small(ctx, seed):
+    p = I.volume_com(seed, grid=(32, 16, 16))
+    say("volume_com small", seed, p.n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+    print(r["path"], r["passes"], r["iters_newton"], flush=True)
+
+
+def test_volume_com_ragged_2d(ctx):
+    """n = 2 * 37^2 = 2738 is not a multiple of the vector width: rows are padded."""
+    p = I.volume_com(2, grid=(74, 37))
+    say("volume_com 2d ragged", p.n)
+    x, r, fm = run(ctx, p)
+    check(p, x, r, orc(p), fm)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_volume_com_full_size(ctx, seed):
+    p = I.volume_com(seed)
+    say("volume_com full", seed, p.n)
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    check(p, x, r, ref, fm)
+    print("path", r["path"], "passes", r["passes"], "newton", r["iters_newton"], flush=True)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 6, 8])
+def test_coupled_row_counts(ctx, m):
+    """Random coupled rows, planted so that about half are active."""
+    rng = np.random.default_rng(100 + m)
+    n = 6000
+    y = rng.uniform(-0.2, 1.2, n).astype(np.float32)
+    A = (rng.standard_normal((m, n)) / n).astype(np.float32)
+    A64 = A.astype(np.float64)
+    lam = np.where(np.arange(m) % 2 == 0, rng.uniform(1, 5, m) * n, 0.0)
+    xs, _ = P.clip_map(y.astype(np.float64), A64, lam, I.LO, I.HI)
+    b = A64 @ xs + np.where(lam > 0, 0.0, 1e-3)
+    p = I.Problem("coupled", y, A, b, C=1e12)
+    say("coupled m", m)
+    x, r, fm = run(ctx, p)
+    check(p, x, r, orc(p), fm)
+
+
+def test_coupled_paper_ncp_and_no_stage1(ctx):
+    p = I.volume_com(0, grid=(32, 16, 16))
+    ref = orc(p)
+    for params in ({"ncp": "paper"}, {"stage1": 0}, {"ncp": "paper", "stage1": 0}):
+        say("coupled variant", params)
+        x, r, fm = run(ctx, p, params=params)
+        check(p, x, r, ref, fm)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_bisect_rule(ctx):
+    """The printed midpoint rule (Alg. 1) with a tight tol_B reaches the same x."""
+    p = I.volume_2d(3, vf=0.4)
+    x, r, fm = run(ctx, p, params={"search": "bisect"})
+    check(p, x, r, orc(p), fm)
+    assert r["iters_search"] >= 30
+    q = I.compliance_3d(1, n=100000)
+    x, r, fm = run(ctx, q, params={"search": "bisect", "tol_b": 1e-14})
+    check(q, x, r, orc(q), fm)
+
+
+def test_infeasible_single_row(ctx):
+    rng = np.random.default_rng(12)
+    n = 5000
+    y = rng.uniform(-0.5, 1.5, n).astype(np.float32)
+    a = rng.standard_normal(n).astype(np.float32)
+    a64 = a.astype(np.float64)
+    xmin = np.where(a64 > 0, I.LO, I.HI)
+    b = float(a64 @ xmin) - 1.0
+    p = I.Problem("single", y, a.reshape(1, n), np.array([b]))
+    x, r, fm = run(ctx, p)
+    ref = orc(p)
+    assert r["outcome"] == "infeasible"
+    check(p, x, r, ref, fm)
+
+
+def test_nonfinite_input(ctx):
+    p = I.compliance_3d(3, n=10000)
+    p.y[17] = np.nan
+    x, r, fm = run(ctx, p, want_mask=False)
+    assert r["outcome"] == "nonfinite"
+
+
+def test_inactive_bit_exact(ctx):
+    p = I.compliance_3d(0, n=50000)
+    p.b[:] = 1e9
+    x, r, _ = run(ctx, p, want_mask=False)
+    assert r["outcome"] == "inactive"
+    np.testing.assert_array_equal(x, np.clip(p.y, np.float32(p.lo), np.float32(p.hi)).astype(np.float32)
+                                  if False else np.clip(p.y.astype(np.float64), p.lo, p.hi).astype(np.float32))
+
+
+def test_repeat_is_bitwise_identical(ctx):
+    p = I.volume_com(0, grid=(48, 24, 24))
+    x1, r1, _ = run(ctx, p, want_mask=False)
+    x2, r2, _ = run(ctx, p, want_mask=False)
+    np.testing.assert_array_equal(x1, x2)
+    assert r1["lam"] == r2["lam"]
+
+
+def test_invalid_arguments(ctx):
+    from paper_2511_13905_amd import _native as N
+    p = I.compliance_3d(0, n=4096)
+    y, A = dev(p.y), dev(p.A)
+    bad = [dict(lo=1.0, hi=0.5), dict(lo=float("nan"))]
+    for kw in bad:
+        args = dict(lo=p.lo, hi=p.hi)
+        args.update(kw)
+        with pytest.raises(N.PgdtoError) as e:
+            ctx.project("single", y, A, p.b, args["lo"], args["hi"])
+        assert e.value.status == N.ERR_ARG
+    with pytest.raises(N.PgdtoError):
+        ctx.project("single", y, A, p.b, p.lo, p.hi, x=y)          # x aliases y
+    with pytest.raises(N.PgdtoError):
+        ctx.project("single", y, A, [float("nan")], p.lo, p.hi)
+    q = I.multi_material(0, n_per=1000)
+    with pytest.raises(N.PgdtoError):
+        ctx.project("independent", dev(q.y), dev(q.A), q.b, q.lo, q.hi, offsets=[0, 10, 5, 3000, 4000])
+    with pytest.raises(N.PgdtoError):                                # misaligned y
+        yy = torch.zeros(4097, dtype=torch.float32, device="cuda:0")[1:]
+        ctx.project("single", yy, A, p.b, p.lo, p.hi)
+
+
+# ------------------------------------------------------------------ Algorithm 3 step
+
+@pytest.mark.parametrize("t,rule", [(60, "pr+"), (0, "pr+"), (60, "fr"), (10, "none")])
+def test_pgd_step_single(ctx, t, rule):
+    st = I.pgd_compliance_3d(1, t=t, n=200003)
+    say("pgd_step", t, rule, st.rho.size)
+    A = st.problem.A
+    d = dev(st.d_prev)
+    x, out = ctx.pgd_step("single", dev(A), dev(st.rho), dev(st.rho_prev), dev(st.grad), dev(st.grad_prev), d,
+                          st.g, st.G, t, I.LO, I.HI, cg_rule=rule)
+    torch.cuda.synchronize()
+    ref = oracle.pgd_step("single", st.rho, st.rho_prev, st.grad, st.grad_prev, st.d_prev, A, st.g, st.G, t,
+                          I.LO, I.HI, p=oracle.PgdParams(cg_rule=rule), stream_dtype=np.float32)
+    assert out["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+    assert out["beta"] == pytest.approx(ref["beta"], rel=1e-9, abs=1e-15)
+    assert out["used_fallback"] == ref["used_fallback"]
+    np.testing.assert_allclose(d.cpu().numpy(), ref["d"], rtol=1e-6, atol=1e-7)
+    prob = I.Problem("single", ref["rho_tilde"], A, ref["b"])
+    check(prob, x.cpu().numpy(), out["proj"], ref["proj"])
+    assert out["rel_change"] == pytest.approx(ref["rel_change"], rel=1e-5)
+
+
+def test_pgd_step_coupled(ctx):
+    p = I.volume_com(0, grid=(32, 16, 16))
+    rng = np.random.default_rng(5)
+    n = p.n
+    rho = np.clip(rng.uniform(0, 1, n), I.LO, I.HI).astype(np.float32)
+    grad = rng.standard_normal(n).astype(np.float32)
+    rho_prev = (rho - 0.01 * rng.standard_normal(n)).astype(np.float32)
+    grad_prev = (grad + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    d_prev = (-grad_prev).astype(np.float32)
+    A64 = p.A.astype(np.float64)
+    g = A64 @ rho.astype(np.float64)
+    G = p.b.copy()
+    d = dev(d_prev)
+    x, out = ctx.pgd_step("coupled", dev(p.A), dev(rho), dev(rho_prev), dev(grad), dev(grad_prev), d, g, G, 70,
+                          I.LO, I.HI, C=p.C)
+    ref = oracle.pgd_step("coupled", rho, rho_prev, grad, grad_prev, d_prev, p.A, g, G, 70, I.LO, I.HI, C=p.C,
+                          stream_dtype=np.float32)
+    assert out["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+    prob = I.Problem("coupled", ref["rho_tilde"], p.A, ref["b"], C=p.C)
+    check(prob, x.cpu().numpy(), out["proj"], ref["proj"])
