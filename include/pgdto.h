@@ -241,6 +241,16 @@ int pgdto_batch_destroy(pgdto_batch* b);
 const char* pgdto_status_string(int status);
 int pgdto_version(void);
 
+/* Tracing: when the environment variable PGDTO_TRACE is set (non-zero) at
+ * context creation, every launch records, per streaming pass, eight 64-bit
+ * values on the device's 100 MHz clock: workgroup 0's (phase << 56 | pass
+ * start), element loop done, all flags seen, totals reduced, synchronisation
+ * left, control done; the last workgroup's loop done and totals seen.  This
+ * copies up to max_records records (8 values each) of the last launch to host
+ * memory `out` and clears them; returns the number of records copied
+ * (0 when tracing is off) or a negative status. */
+int pgdto_trace_read(pgdto_ctx* ctx, uint64_t* out, int max_records);
+
 /* Layout introspection for language bindings: sizeof of the public structs.
  * which: 0 pgdto_problem, 1 pgdto_params, 2 pgdto_result, 3 pgdto_pgd_args,
  * 4 pgdto_pgd_out, 5 pgdto_batch_cfg.  Returns 0 for an unknown index. */

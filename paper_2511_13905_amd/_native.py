@@ -110,6 +110,7 @@ SIGNATURES = {
     "pgdto_status_string": (C.c_char_p, [C.c_int]),
     "pgdto_version": (C.c_int, []),
     "pgdto_struct_size": (C.c_size_t, [C.c_int]),
+    "pgdto_trace_read": (C.c_int, [_VP, C.POINTER(C.c_uint64), C.c_int]),
 }
 
 _lib = None

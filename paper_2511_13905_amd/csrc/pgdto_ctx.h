@@ -8,9 +8,11 @@
 struct pgdto_ctx {
   int device = 0;
   double* part = nullptr;        // per-tile partial sums, double-buffered
-  uint32_t* bar = nullptr;       // grid-barrier words
+  uint64_t* sync = nullptr;      // grid synchronisation words
+  uint64_t launch_seq = 0;       // epoch base of the next launch
   void* res_dev = nullptr;       // device staging of a result struct
   void* res_host = nullptr;      // pinned host staging
+  uint64_t* trace = nullptr;     // per-pass timestamps when PGDTO_TRACE is set
   int coop_cap[2][2][PGDTO_MAX_M + 1] = {};   // co-resident workgroups per kernel
   int last_grid = 0;
   int last_ntiles = 0;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -65,6 +66,22 @@ extern "C" const char* pgdto_status_string(int s) {
 
 extern "C" int pgdto_version(void) { return PGDTO_VERSION; }
 
+extern "C" int pgdto_trace_read(pgdto_ctx* c, uint64_t* out, int max_records) {
+  if (!c || !out) return PGDTO_ERR_ARG;
+  if (!c->trace) return 0;
+  if (max_records < 0) {   // per-workgroup table: TRACE_WG_PASSES x 1024 x (start, end)
+    if (hipDeviceSynchronize() != hipSuccess) return PGDTO_ERR_HIP;
+    if (hipMemcpy(out, c->trace + (size_t)TRACE_MAX * TRACE_W, sizeof(uint64_t) * TRACE_WG_PASSES * 1024 * 2,
+                  hipMemcpyDeviceToHost) != hipSuccess) return PGDTO_ERR_HIP;
+    return TRACE_WG_PASSES;
+  }
+  const int n = max_records < TRACE_MAX ? max_records : TRACE_MAX;
+  if (hipDeviceSynchronize() != hipSuccess) return PGDTO_ERR_HIP;
+  if (hipMemcpy(out, c->trace, sizeof(uint64_t) * TRACE_W * n, hipMemcpyDeviceToHost) != hipSuccess) return PGDTO_ERR_HIP;
+  if (hipMemset(c->trace, 0, sizeof(uint64_t) * TRACE_WORDS) != hipSuccess) return PGDTO_ERR_HIP;
+  return n;
+}
+
 extern "C" size_t pgdto_struct_size(int which) {
   switch (which) {
     case 0: return sizeof(pgdto_problem);
@@ -87,11 +104,18 @@ extern "C" int pgdto_ctx_create(int device, pgdto_ctx** out) {
   if (!c) return PGDTO_ERR_NOMEM;
   c->device = device;
   int ok = hipMalloc(&c->part, sizeof(double) * PART_DOUBLES) == hipSuccess;
-  ok = ok && hipMalloc(&c->bar, 64 * sizeof(uint32_t)) == hipSuccess;
+  ok = ok && hipMalloc(&c->sync, SYNC_WORDS * sizeof(uint64_t)) == hipSuccess;
   ok = ok && hipMalloc(&c->res_dev, sizeof(pgdto_pgd_out)) == hipSuccess;
   ok = ok && hipHostMalloc(&c->res_host, sizeof(pgdto_pgd_out), hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipMemset(c->bar, 0, 64 * sizeof(uint32_t)) == hipSuccess;
+  ok = ok && hipMemset(c->sync, 0, SYNC_WORDS * sizeof(uint64_t)) == hipSuccess;
   ok = ok && hipMemset(c->part, 0, sizeof(double) * PART_DOUBLES) == hipSuccess;
+  {
+    const char* tv = getenv("PGDTO_TRACE");
+    if (tv && tv[0] && tv[0] != '0') {
+      ok = ok && hipMalloc(&c->trace, sizeof(uint64_t) * TRACE_WORDS) == hipSuccess;
+      ok = ok && hipMemset(c->trace, 0, sizeof(uint64_t) * TRACE_WORDS) == hipSuccess;
+    }
+  }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     pgdto_ctx_destroy(c);
@@ -106,9 +130,10 @@ extern "C" int pgdto_ctx_destroy(pgdto_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->part) (void)hipFree(c->part);
-  if (c->bar) (void)hipFree(c->bar);
+  if (c->sync) (void)hipFree(c->sync);
   if (c->res_dev) (void)hipFree(c->res_dev);
   if (c->res_host) (void)hipHostFree(c->res_host);
+  if (c->trace) (void)hipFree(c->trace);
   delete c;
   return PGDTO_OK;
 }
@@ -204,8 +229,10 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
     d.off[1] = n;
   }
   // tiles: size depends only on n and dtype
+  // 1-D kernel: two workgroups per CU (512 tiles); coupled: one (256 tiles)
   const int64_t unit = tile_unit(pr->dtype);
-  int64_t tile = (n + TARGET_TILES - 1) / TARGET_TILES;
+  const int64_t target = pr->kind == PGDTO_COUPLED ? TARGET_TILES / 2 : TARGET_TILES;
+  int64_t tile = (n + target - 1) / target;
   tile = std::max<int64_t>(unit, (tile + unit - 1) / unit * unit);
   d.tile_elems = tile;
   int32_t tb = 0;
@@ -231,7 +258,10 @@ int grid_for(pgdto_ctx* c, const Desc& d) {
 
 int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_pgd) {
   d.part = c->part;
-  d.bar = c->bar;
+  d.sync = c->sync;
+  c->launch_seq += 1;
+  d.epoch0 = c->launch_seq << 20;
+  d.trace = c->trace;
   d.result = result_dev;
   d.pgd = is_pgd ? 1 : 0;
   const int grid = grid_for(c, d);
@@ -242,7 +272,7 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   hipError_t e = launch_solve(d, grid, s, true);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    (void)launch_mark_error(c->bar, result_dev, is_pgd ? 1 : 0, s);
+    (void)launch_mark_error(result_dev, is_pgd ? 1 : 0, s);
     return PGDTO_ERR_HIP;
   }
   c->last_grid = grid;

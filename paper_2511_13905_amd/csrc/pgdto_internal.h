@@ -11,11 +11,14 @@ namespace pgdto {
 constexpr int BLOCK = 512;                 // threads per workgroup (8 wave64)
 constexpr int NWAVE = BLOCK / 64;
 constexpr int NT = 2;                      // trial multipliers per 1-D search pass
-constexpr int TARGET_TILES = 256;          // tiles per instance (tile size follows n)
+constexpr int TARGET_TILES = 512;          // tiles per instance (tile size follows n)
 constexpr int MAX_TILES = TARGET_TILES + PGDTO_MAX_BLOCKS + 8;
-constexpr int TILES_PAD = 384;             // stride of the partial-sum table
+constexpr int TILES_PAD = 704;             // stride of the partial-sum table
 constexpr int VMAX = 112;                  // partial values per tile (coupled, m = 8)
 constexpr int PART_DOUBLES = 2 * VMAX * TILES_PAD;   // double-buffered
+constexpr int GMAX = 1024;                 // workgroups of one launch (upper bound)
+constexpr int TOT_MAX = 1024;              // per-segment totals of one pass
+constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + 16 + 16 + TOT_MAX;   // uint64 words
 
 // Bounded spin of the grid barrier: about a second of waiting before the
 // workgroup gives up, flags PGDTO_ERR_TIMEOUT and leaves the kernel.
@@ -48,9 +51,20 @@ struct Desc {
   double alpha_max, alpha_fallback, omega, eps_alpha, tol_stop;
   // workspace
   double* part;          // [2][VMAX][TILES_PAD]
-  uint32_t* bar;         // [0] barrier arrivals, [1] exits, [2] error flag
+  uint64_t* sync;        // epoch flags, go word, error word, totals
+  uint64_t epoch0;       // launch-unique epoch base (pass p publishes epoch0 + p + 1)
   void* result;          // pgdto_result (pgd: pgdto_pgd_out)
+  uint64_t* trace;       // optional [TRACE_MAX][4] per-pass timestamps (workgroup 0)
 };
+
+// Per-pass trace record (100 MHz device clock), TRACE_W words: [0] phase << 56
+// | start, [1] element loop done, [2] workgroup 0 saw every flag, [3] totals
+// reduced, [4] synchronisation left, [5] control done; last workgroup:
+// [6] loop done, [7] saw the totals.
+constexpr int TRACE_MAX = 128;
+constexpr int TRACE_W = 8;
+constexpr int TRACE_WG_PASSES = 16;        // per-workgroup loop times kept for the first passes
+constexpr size_t TRACE_WORDS = (size_t)TRACE_MAX * TRACE_W + (size_t)TRACE_WG_PASSES * 1024 * 2;
 
 // Tiling: the tile size depends only on n and the dtype, so that an
 // instance's reduction order (and hence its bits) does not depend on how many
@@ -64,5 +78,5 @@ inline int64_t tile_unit(int dtype) { return (int64_t)BLOCK * vec_elems(dtype) *
 namespace pgdto {
 hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative);
 int max_coresident(int kind, int dtype, int m, int device);
-hipError_t launch_mark_error(uint32_t* bar, void* result, int is_pgd, hipStream_t stream);
+hipError_t launch_mark_error(void* result, int is_pgd, hipStream_t stream);
 }  // namespace pgdto

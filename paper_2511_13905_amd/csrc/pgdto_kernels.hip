@@ -2,11 +2,11 @@
 //
 // One persistent cooperative launch solves a whole projection: every pass
 // streams y (and the constraint rows) once, each workgroup reduces its tiles
-// into per-tile partial sums, a grid barrier follows, and then EVERY
-// workgroup reduces the per-tile partials in the same fixed order and runs
-// the same float64 control logic (bracket update, Newton step, line search)
-// on bit-identical inputs.  All workgroups therefore agree on the next pass
-// without a second barrier and without the host.
+// into per-tile partial sums and publishes an epoch flag; workgroup 0 sums
+// the per-tile partials in a fixed order and broadcasts the totals; then
+// EVERY workgroup runs the same float64 control logic (bracket update,
+// Newton step, line search) on bit-identical totals, so all workgroups agree
+// on the next pass without the host.
 //
 // Paper references: x(lam) = clip(y - A^T lam) (Theorems 1/2, eq. delta_y),
 // h (eq. h), J = A D A^T + kappa I (eq. reg_jacobian), Algorithm 1 (bracket
@@ -17,11 +17,13 @@
 // Precision: streams are float32 or float64 in HBM; every per-element
 // operation is done in float64 (the FP64 vector rate of CDNA4 is half the
 // FP32 rate, far above what an 8 B/element stream needs), sums are float64
-// per thread, then a fixed wave/LDS tree, then a fixed-order cross-tile sum.
+// per thread, then a fixed LDS/wave tree, then a fixed-order cross-tile sum.
 
 #include "pgdto_internal.h"
 
 #include <math.h>
+
+#include <type_traits>
 
 namespace pgdto {
 
@@ -44,14 +46,30 @@ template <typename T> struct VT;
 template <> struct VT<float> { static constexpr int N = 4; };
 template <> struct VT<double> { static constexpr int N = 2; };
 
+// Global-address-space views of generic pointers (the pointers come from the
+// LDS copy of the descriptor; without the cast the compiler emits flat
+// accesses, which also wait on the LDS counter).
 template <typename T>
-__device__ __forceinline__ void ld_vec(const T* __restrict__ p, int64_t e0, int64_t n, bool full, T* o) {
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr_w(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ void ld_vec(const T* __restrict__ p0, int64_t e0, int64_t n, bool full, T* o) {
+  const auto p = gptr(p0);
   if (full) {
     if constexpr (sizeof(T) == 4) {
-      const float4 q = *reinterpret_cast<const float4*>(p + e0);
+      const f32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) f32x4*>(p + e0);
       o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
     } else {
-      const double2 q = *reinterpret_cast<const double2*>(p + e0);
+      const f64x2 q = *reinterpret_cast<const __attribute__((address_space(1))) f64x2*>(p + e0);
       o[0] = q.x; o[1] = q.y;
     }
   } else {
@@ -61,12 +79,15 @@ __device__ __forceinline__ void ld_vec(const T* __restrict__ p, int64_t e0, int6
 }
 
 template <typename T>
-__device__ __forceinline__ void st_vec(T* __restrict__ p, int64_t e0, uint32_t mask, bool full, const T* v) {
+__device__ __forceinline__ void st_vec(T* __restrict__ p0, int64_t e0, uint32_t mask, bool full, const T* v) {
+  const auto p = gptr_w(p0);
   if (full) {
     if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4*>(p + e0) = make_float4(v[0], v[1], v[2], v[3]);
+      const f32x4 q = {v[0], v[1], v[2], v[3]};
+      *reinterpret_cast<__attribute__((address_space(1))) f32x4*>(p + e0) = q;
     } else {
-      *reinterpret_cast<double2*>(p + e0) = make_double2(v[0], v[1]);
+      const f64x2 q = {v[0], v[1]};
+      *reinterpret_cast<__attribute__((address_space(1))) f64x2*>(p + e0) = q;
     }
   } else {
 #pragma unroll
@@ -95,35 +116,41 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Reduce NV per-thread values over the workgroup and store them as the
 // partials of `tile` (value-major layout).  Values whose bit is set in
-// `maxmask` are maxima, the rest sums.  Fixed order: xor butterfly inside the
-// wave, then waves 0..7 in order.
+// `maxmask` are maxima, the rest sums.  Fixed order: the values go through
+// LDS in chunks of 8; wave w reduces value c + w of chunk c, each lane first
+// summing 8 threads' entries in a fixed order, then an xor butterfly.
 template <int NV>
 __device__ __forceinline__ void block_to_part(const double (&acc)[NV], int nv, uint64_t maxmask,
                                               double* red, double* pb, int tile) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
+  for (int c = 0; c < NV; c += NWAVE) {
+#pragma unroll
+    for (int j = 0; j < NWAVE; ++j)
+      if (c + j < NV) red[j * BLOCK + tid] = acc[c + j];
+    __syncthreads();
+    const int v = c + w;
     if (v < nv) {
       const bool mx = v < 64 && ((maxmask >> v) & 1);
-      const double r = mx ? wave_max(acc[v]) : wave_sum(acc[v]);
-      if (lane == 0) red[w * VMAX + v] = r;
-    }
-  }
-  __syncthreads();
-  for (int v = threadIdx.x; v < nv; v += BLOCK) {
-    const bool mx = v < 64 && ((maxmask >> v) & 1);
-    double r = red[v];
+      const double* col = red + w * BLOCK;
+      double r = col[lane];
 #pragma unroll
-    for (int q = 1; q < NWAVE; ++q) r = mx ? fmax(r, red[q * VMAX + v]) : r + red[q * VMAX + v];
-    pb[v * TILES_PAD + tile] = r;
+      for (int k = 1; k < BLOCK / 64; ++k) {
+        const double q = col[k * 64 + lane];
+        r = mx ? fmax(r, q) : r + q;
+      }
+      r = mx ? wave_max(r) : wave_sum(r);
+      if (lane == 0) pb[v * TILES_PAD + tile] = r;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Reduce the per-tile partials of every segment: tot[s * nv + v].  Every
 // workgroup runs this on the same data in the same order.
 __device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const int32_t* tile_base,
                              int nseg, double* tot) {
+  constexpr int LMAX = 6;               // loads in flight per thread
   const int pairs = nseg * nv;
   int P = 64;
   while (P > 1 && pairs * P > BLOCK) P >>= 1;
@@ -138,9 +165,15 @@ __device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const i
     double r = mx ? -INFINITY : 0.0;
     if (act) {
       const int te = tile_base[s + 1];
-      for (int t = tile_base[s] + g; t < te; t += P) {
-        const double q = pb[v * TILES_PAD + t];
-        r = mx ? fmax(r, q) : r + q;
+      for (int t0 = tile_base[s] + g; t0 < te; t0 += LMAX * P) {
+        double q[LMAX];
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) {
+          const int t = t0 + k * P;
+          q[k] = (t < te) ? pb[v * TILES_PAD + t] : (mx ? -INFINITY : 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) r = mx ? fmax(r, q[k]) : r + q[k];
       }
     }
     for (int o = P >> 1; o > 0; o >>= 1) {
@@ -152,50 +185,132 @@ __device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const i
   __syncthreads();
 }
 
-// ------------------------------------------------------------------ grid barrier
+// ------------------------------------------------------------------ tracing
 
-// Arrive-and-spin barrier on a monotonically increasing counter (reset by the
-// last workgroup to leave the kernel).  The spin is bounded: on expiry the
-// workgroup raises the error word and every workgroup leaves its loop.
-__device__ bool grid_barrier(uint32_t* bar, uint32_t nwg, uint32_t& target, int32_t* abort_flag) {
+__device__ __forceinline__ uint64_t clk() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ void trace_put(const Desc& d, int pass, int slot, uint64_t v) {
+  if (d.trace && blockIdx.x == 0 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
+}
+// per-workgroup (loop start, loop end) of each pass, after the per-pass records
+__device__ __forceinline__ void trace_wg(const Desc& d, int pass, uint64_t t_start, uint64_t t_end) {
+  if (d.trace && threadIdx.x == 0 && pass < TRACE_WG_PASSES)
+    d.trace[TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + blockIdx.x) * 2 + 0] = t_start,
+    d.trace[TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + blockIdx.x) * 2 + 1] = t_end;
+}
+// records of the last workgroup (slots 6, 7)
+__device__ __forceinline__ void trace_last(const Desc& d, int pass, int slot, uint64_t v) {
+  if (d.trace && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
+}
+
+// ------------------------------------------------------------------ grid synchronisation
+
+// One pass ends with every workgroup publishing a launch-unique epoch on its
+// own cache line (no shared counter: device-scope atomics on one address
+// serialise at the memory side and cost ~G x 70 ns).  Workgroup 0 waits for
+// all flags with all its threads, reduces the per-tile partials once (fixed
+// order), stores the totals and raises `go`; the other workgroups wait on
+// `go` and read the totals.  Every wait is bounded: on expiry the error word
+// records this launch's epoch and every workgroup leaves.
+constexpr int FLAG_STRIDE = 16;     // uint64 per flag: one 128-byte line each
+
+struct SyncWords {
+  uint64_t* flags;   // [GMAX * FLAG_STRIDE]
+  uint64_t* go;      // one line
+  uint64_t* err;     // one line: epoch of the launch that timed out
+  double* totals;    // [TOT_MAX]
+};
+
+__device__ __forceinline__ SyncWords sync_words(const Desc& d) {
+  SyncWords w;
+  w.flags = d.sync;
+  w.go = d.sync + (size_t)GMAX * FLAG_STRIDE;
+  w.err = w.go + FLAG_STRIDE;
+  w.totals = (double*)(w.err + FLAG_STRIDE);
+  return w;
+}
+
+__device__ bool grid_reduce(const Desc& d, uint64_t epoch, const double* pb, int nv, uint64_t maxmask,
+                            int nseg, double* tot, int32_t* abort_flag, int pass_no) {
+  const SyncWords W = sync_words(d);
+  const int G = gridDim.x;
+  const int ntot = nseg * nv;
   __syncthreads();
-  target += nwg;
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    *abort_flag = 0;
+    __hip_atomic_store(&W.flags[(size_t)blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    bool ok = true;
+    for (int w = threadIdx.x; w < G && ok; w += BLOCK) {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&W.flags[(size_t)w * FLAG_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT) { ok = false; break; }
+      }
+    }
+    if (!ok) atomicOr(abort_flag, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (*abort_flag) __hip_atomic_store(W.err, d.epoch0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (*abort_flag) return false;
+    trace_put(d, pass_no, 2, clk());
+    reduce_tiles(pb, nv, maxmask, d.tile_base, nseg, tot);
+    trace_put(d, pass_no, 3, clk());
+    for (int i = threadIdx.x; i < ntot; i += BLOCK) W.totals[i] = tot[i];
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(W.go, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  trace_last(d, pass_no, 6, clk());
+  if (threadIdx.x == 0) {
     uint32_t spins = 0;
     bool ok = true;
-    while (__hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(W.go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > SPIN_LIMIT ||
-          __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      if (++spins > SPIN_LIMIT || __hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == d.epoch0) {
         ok = false;
         break;
       }
     }
-    __threadfence();
-    if (!ok) __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *abort_flag = ok ? 0 : 1;
-  }
-  __syncthreads();
-  return *abort_flag == 0;
-}
-
-// The last workgroup out resets the barrier words and reports a timeout.
-__device__ void kernel_exit(uint32_t* bar, uint32_t nwg, int32_t* err_field) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == nwg - 1) {
-      const uint32_t e = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (e != 0u && err_field) *err_field = PGDTO_ERR_TIMEOUT;
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) {
+      __hip_atomic_store(W.err, d.epoch0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *abort_flag = 1;
     }
   }
+  __syncthreads();
+  if (*abort_flag) return false;
+  trace_last(d, pass_no, 7, clk());
+  for (int i = threadIdx.x; i < ntot; i += BLOCK) tot[i] = W.totals[i];
+  __syncthreads();
+  return true;
+}
+
+// Workgroup 0 reports a timeout of this launch in the result.
+__device__ void report_error(const Desc& d, int32_t* err_field) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && err_field) {
+    const SyncWords W = sync_words(d);
+    if (__hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == d.epoch0)
+      *err_field = PGDTO_ERR_TIMEOUT;
+  }
+}
+
+// ------------------------------------------------------------------ descriptor in LDS
+
+// The launch descriptor is the kernel's only argument.  Each workgroup copies
+// it once from the kernarg segment into LDS and reads it from there; naming
+// the by-value parameter would make the compiler copy it to private memory
+// for every lane.
+__device__ __forceinline__ void load_desc(Desc& sd) {
+  const uint32_t* src = (const uint32_t*)__builtin_amdgcn_kernarg_segment_ptr();
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&sd);
+  for (int i = threadIdx.x; i < (int)(sizeof(Desc) / 4); i += BLOCK) dst[i] = src[i];
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ tile geometry
@@ -244,6 +359,32 @@ __device__ __forceinline__ bool slot(const TileGeom& g, int k, int64_t& e0, bool
   return mask != 0;
 }
 
+// Stream a tile in chunks of U vector slots per thread: the loads of all U
+// slots (NS streams each) are issued before any of them is used, so each
+// wave keeps U * NS 16-byte loads in flight.  f(buf, e0, mask, full) gets the
+// NS loaded vectors of one slot.
+template <typename T, int NS, int U, class F>
+__device__ __forceinline__ void stream_tile(const TileGeom& g, int64_t n, const T* const* ptrs, F&& f) {
+  constexpr int V = VT<T>::N;
+  for (int k0 = 0; k0 < g.nsweep; k0 += U) {
+    T buf[U][NS][V];
+    int64_t e0[U];
+    uint32_t mask[U];
+    bool full[U], ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ok[u] = (k0 + u < g.nsweep) && slot<T>(g, k0 + u, e0[u], full[u], mask[u]);
+      if (ok[u]) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) ld_vec<T>(ptrs[q], e0[u], n, full[u], buf[u][q]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) f(buf[u], e0[u], mask[u], full[u]);
+  }
+}
+
 // ------------------------------------------------------------------ 1-D search control
 
 // Per-row bracket state of a 1-D search on phi(lam) = a.x(lam) - b - kappa lam
@@ -262,7 +403,7 @@ struct Search {
 
 __device__ __forceinline__ bool inside(double v, double lo, double hi) { return v > lo && v < hi; }
 
-__device__ void search_pick(Search& S, int s, int mode) {
+__device__ void search_pick(Search& S, int s, int mode, bool lean) {
   const double lo = S.lo[s], hi = S.hi[s];
   const double mid = 0.5 * (lo + hi);
   if (mode == PGDTO_SEARCH_BISECT) {
@@ -273,13 +414,20 @@ __device__ void search_pick(Search& S, int s, int mode) {
   const double sec = lo + S.flo[s] * ((hi - lo) / (S.flo[s] - S.fhi[s]));
   const double nlo = S.slo[s] > 0.0 ? lo + S.flo[s] / S.slo[s] : NAN;
   const double nhi = S.shi[s] > 0.0 ? hi + S.fhi[s] / S.shi[s] : NAN;
+  // First trial: the Newton point from the lower end (the tangent of the
+  // piecewise-linear dual there), else the secant, else the midpoint.
+  // lean (compute-bound passes): a second trial, the midpoint, only when the
+  // previous pass did not halve the bracket.  Otherwise (streaming passes, where
+  // a second trial is almost free) the Newton point from the upper end, or the
+  // midpoint when the bracket did not halve.
   double t0 = inside(nlo, lo, hi) ? nlo : (inside(sec, lo, hi) ? sec : mid);
+  if (!inside(t0, lo, hi)) t0 = mid;
   double t1;
-  if (!S.shrunk[s]) t1 = mid;                          // safeguard: force a halving
+  if (lean) t1 = S.shrunk[s] ? NAN : mid;
+  else if (!S.shrunk[s]) t1 = mid;
   else if (inside(nhi, lo, hi) && nhi != t0) t1 = nhi;
   else if (inside(sec, lo, hi) && sec != t0) t1 = sec;
   else t1 = mid;
-  if (!inside(t0, lo, hi)) t0 = mid;
   if (t1 == t0 || !inside(t1, lo, hi)) t1 = NAN;
   S.trial[s][0] = t0;
   S.trial[s][1] = t1;
@@ -289,7 +437,7 @@ __device__ void search_pick(Search& S, int s, int mode) {
 // must run.  f0 = phi(0); s0 = -phi'(0); bp = largest breakpoint (the end of
 // Alg. 1's bracket, -y_l); ssat = a.x over the saturated point.
 __device__ bool search_init(Search& S, int s, double f0, double s0, double bp, double ssat,
-                            double b, double kappa, double scale, int mode) {
+                            double b, double kappa, double scale, int mode, bool lean) {
   S.npass[s] = 0;
   S.width[s] = 0.0;
   S.scale[s] = scale;
@@ -319,14 +467,15 @@ __device__ bool search_init(Search& S, int s, double f0, double s0, double bp, d
   S.lo[s] = 0.0; S.flo[s] = f0; S.slo[s] = s0;
   S.hi[s] = bp;  S.fhi[s] = fhi; S.shi[s] = kappa;
   S.state[s] = SEG_SEARCH;
-  search_pick(S, s, mode);
+  search_pick(S, s, mode, lean);
   return true;
 }
 
 // Update row/block s from the sums of one search pass.  fsum[t] = a.x(trial_t),
 // ssum[t] = sum over free elements of a^2 at trial_t.
 __device__ void search_update(Search& S, int s, double f0sum, double f1sum, double s0sum, double s1sum,
-                              double b, double kappa, double tol_n, double tol_b, int max_pass, int mode) {
+                              double b, double kappa, double tol_n, double tol_b, int max_pass, int mode,
+                              bool lean) {
   const double fsum[NT] = {f0sum, f1sum};
   const double ssum[NT] = {s0sum, s1sum};
   const double eps = tol_n * S.scale[s];
@@ -365,7 +514,7 @@ __device__ void search_update(Search& S, int s, double f0sum, double f1sum, doub
     S.state[s] = SEG_DONE;
     return;
   }
-  search_pick(S, s, mode);
+  search_pick(S, s, mode, lean);
 }
 
 // Control parameters, copied once into LDS so that no reference to the
@@ -426,7 +575,7 @@ __device__ __forceinline__ void pgd_scalars(const Desc& d, const double* v, PgdS
 
 struct Sh1D {
   double tot[PGDTO_MAX_BLOCKS * 8];
-  double red[NWAVE * VMAX];
+  double red[NWAVE * BLOCK];
   double bs[PGDTO_MAX_BLOCKS];
   double glob[8];
   Search S;
@@ -435,15 +584,18 @@ struct Sh1D {
 };
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
+__global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
   constexpr int V = VT<T>::N;
   __shared__ Sh1D sh;
+  __shared__ Desc sd;
+  load_desc(sd);
+  const Desc& d = sd;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
-  const double lo = d.lo, hi = d.hi, kappa = d.kappa;
+  const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi), kappa = d.kappa;
 
   if (tid == 0) {
-    sh.phase = d.pgd ? PH_PGD_R : PH_ZERO;
+    sh.phase = PH_ZERO;
     sh.abort_flag = 0;
     sh.passes = 0;
     sh.pg.alpha = 0.0; sh.pg.beta = 0.0; sh.pg.used_fb = 0;
@@ -455,186 +607,61 @@ __global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
   }
   __syncthreads();
 
-  uint32_t target = 0;
   int buf = 0;
   const T* A = (const T*)d.A;
   T* X = (T*)d.x;
   const T* Y = d.pgd ? (const T*)d.x : (const T*)d.y;
 
-  for (;;) {
-    const int ph = sh.phase;
+  int pass_no = 0;
+  if (d.pgd) {
+    // Alg. 3 reductions (pass R), before the main loop so that the resident
+    // registers below are not live across it.
     double* pb = d.part + (size_t)buf * VMAX * TILES_PAD;
-    int nv = 0;
-    uint64_t maxmask = 0;
-
+    const uint64_t t_pass0 = clk();
+    trace_put(d, pass_no, 0, ((uint64_t)PH_PGD_R << 56) | (t_pass0 & 0x00ffffffffffffffull));
+    const int nv = 8;
+    const uint64_t maxmask = 1ull << 6;
     for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
       const TileGeom g = tile_geom<T>(d, tile);
-      const int s = g.seg;
-      if (ph == PH_PGD_R) {
-        nv = 8; maxmask = 1ull << 6;
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        acc[6] = 0.0;
-        const T* R = (const T*)d.rho; const T* RP = (const T*)d.rho_prev;
-        const T* Gr = (const T*)d.grad; const T* GP = (const T*)d.grad_prev;
-        for (int k = 0; k < g.nsweep; ++k) {
-          int64_t e0; bool full; uint32_t mask;
-          if (!slot<T>(g, k, e0, full, mask)) continue;
-          T r[V], a[V], gr[V], rp[V], gp[V];
-          ld_vec<T>(R, e0, d.n, full, r);
-          ld_vec<T>(A, e0, d.n, full, a);
-          ld_vec<T>(Gr, e0, d.n, full, gr);
-          if (!d.zero_step) { ld_vec<T>(RP, e0, d.n, full, rp); ld_vec<T>(GP, e0, d.n, full, gp); }
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      // s = rho_t - rho_{t-1}, y = grad_t - grad_{t-1}: |s|^2, |y|^2, s.y, |g|^2,
+      // g.(g - g_prev), |g_prev|^2, |g|_inf, a.rho_t
+      if (d.zero_step) {
+        const T* ptr[3] = {(const T*)d.rho, (const T*)d.grad, A};
+        stream_tile<T, 3, 1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
-            if (!d.zero_step) {
-              const double sv = f64(r[q]) - f64(rp[q]), yv = f64(gr[q]) - f64(gp[q]);
-              acc[0] = fma(sv, sv, acc[0]);
-              acc[1] = fma(yv, yv, acc[1]);
-              acc[2] = fma(sv, yv, acc[2]);
-              acc[4] = fma(f64(gr[q]), yv, acc[4]);
-              acc[5] = fma(f64(gp[q]), f64(gp[q]), acc[5]);
-            }
-            acc[3] = fma(f64(gr[q]), f64(gr[q]), acc[3]);
-            acc[6] = fmax(acc[6], fabs(f64(gr[q])));
-            acc[7] = fma(f64(a[q]), f64(r[q]), acc[7]);
+            const double r = f64(b[0][q]), gr = f64(b[1][q]), av = f64(b[2][q]);
+            acc[3] = fma(gr, gr, acc[3]);
+            acc[6] = fmax(acc[6], fabs(gr));
+            acc[7] = fma(av, r, acc[7]);
           }
-        }
-        block_to_part<8>(acc, nv, maxmask, sh.red, pb, tile);
-      } else if (ph == PH_ZERO) {
-        nv = 6; maxmask = 1ull << 2;
-        double acc[6] = {0, 0, -INFINITY, 0, 0, 0};
-        const T* R = (const T*)d.rho; const T* Gr = (const T*)d.grad; T* D = (T*)d.dir;
-        const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
-        for (int k = 0; k < g.nsweep; ++k) {
-          int64_t e0; bool full; uint32_t mask;
-          if (!slot<T>(g, k, e0, full, mask)) continue;
-          T yv[V], a[V];
-          ld_vec<T>(A, e0, d.n, full, a);
-          if (d.pgd) {
-            // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t,
-            // materialized in the stream precision (it is the point projected).
-            T r[V], gr[V], dp[V];
-            ld_vec<T>(R, e0, d.n, full, r);
-            ld_vec<T>(Gr, e0, d.n, full, gr);
-            if (!d.zero_step) ld_vec<T>(D, e0, d.n, full, dp);
-            T dn[V], rt[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) {
-              const double dd = d.zero_step ? -f64(gr[q]) : fma(beta, f64(dp[q]), -f64(gr[q]));
-              dn[q] = (T)dd;
-              rt[q] = (T)fma(step, dd, f64(r[q]));
-              yv[q] = rt[q];
-            }
-            st_vec<T>(D, e0, mask, full, dn);
-            st_vec<T>(X, e0, mask, full, rt);
-          } else {
-            ld_vec<T>(Y, e0, d.n, full, yv);
-          }
+        });
+      } else {
+        const T* ptr[5] = {(const T*)d.rho, (const T*)d.grad, A, (const T*)d.rho_prev, (const T*)d.grad_prev};
+        stream_tile<T, 5, 1>(g, d.n, ptr, [&](const T (&b)[5][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
-            const double y = f64(yv[q]), av = f64(a[q]);
-            const double x0 = clampd(y, lo, hi);
-            acc[0] = fma(av, x0, acc[0]);
-            if (y >= lo && y <= hi) acc[1] = fma(av, av, acc[1]);
-            if (av != 0.0) {
-              const double bp = (av > 0.0) ? (y - lo) / av : (y - hi) / av;
-              acc[2] = fmax(acc[2], bp);
-              acc[3] += (av > 0.0) ? av * lo : av * hi;
-            }
-            acc[4] += fabs(av);
-            if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
+            const double r = f64(b[0][q]), gr = f64(b[1][q]), av = f64(b[2][q]);
+            const double sv = r - f64(b[3][q]), gp = f64(b[4][q]), yv = gr - gp;
+            acc[0] = fma(sv, sv, acc[0]);
+            acc[1] = fma(yv, yv, acc[1]);
+            acc[2] = fma(sv, yv, acc[2]);
+            acc[3] = fma(gr, gr, acc[3]);
+            acc[4] = fma(gr, yv, acc[4]);
+            acc[5] = fma(gp, gp, acc[5]);
+            acc[6] = fmax(acc[6], fabs(gr));
+            acc[7] = fma(av, r, acc[7]);
           }
-        }
-        block_to_part<6>(acc, nv, maxmask, sh.red, pb, tile);
-      } else if (ph == PH_SEARCH) {
-        nv = 2 * NT; maxmask = 0;
-        if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
-        double acc[2 * NT] = {0, 0, 0, 0};
-        double lt[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) lt[t] = sh.S.trial[s][t];
-        const bool two = (lt[1] == lt[1]);
-        for (int k = 0; k < g.nsweep; ++k) {
-          int64_t e0; bool full; uint32_t mask;
-          if (!slot<T>(g, k, e0, full, mask)) continue;
-          T yv[V], a[V];
-          ld_vec<T>(Y, e0, d.n, full, yv);
-          ld_vec<T>(A, e0, d.n, full, a);
-#pragma unroll
-          for (int q = 0; q < V; ++q) {
-            if (!(mask & (1u << q))) continue;
-            const double av = f64(a[q]), a2 = av * av;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              if (t == 1 && !two) break;
-              const double z = fma(-lt[t], av, f64(yv[q]));
-              acc[2 * t] = fma(av, clampd(z, lo, hi), acc[2 * t]);
-              if (z >= lo && z <= hi) acc[2 * t + 1] += a2;
-            }
-          }
-        }
-        block_to_part<2 * NT>(acc, nv, maxmask, sh.red, pb, tile);
-      } else {  // PH_FINAL
-        nv = 4; maxmask = 0;
-        double acc[4] = {0, 0, 0, 0};
-        const double lam = sh.S.lam[s];
-        const T* R = (const T*)d.rho;
-        const int lane = tid & 63;
-        for (int k = 0; k < g.nsweep; ++k) {
-          int64_t e0; bool full; uint32_t mask;
-          const bool any = slot<T>(g, k, e0, full, mask);
-          uint32_t bits = 0;
-          if (any) {
-            T yv[V], a[V], r[V];
-            ld_vec<T>(Y, e0, d.n, full, yv);
-            ld_vec<T>(A, e0, d.n, full, a);
-            if (d.pgd) ld_vec<T>(R, e0, d.n, full, r);
-            T xo[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) {
-              const double z = fma(-lam, f64(a[q]), f64(yv[q]));
-              xo[q] = (T)clampd(z, lo, hi);
-              if (!(mask & (1u << q))) continue;
-              const double xr = (double)xo[q];
-              acc[0] = fma(f64(a[q]), xr, acc[0]);
-              if (z >= lo && z <= hi) { acc[1] += 1.0; bits |= 1u << q; }
-              if (d.pgd) {
-                const double df = xr - f64(r[q]);
-                acc[2] = fma(df, df, acc[2]);
-                acc[3] = fma(xr, xr, acc[3]);
-              }
-            }
-            st_vec<T>(X, e0, mask, full, xo);
-          }
-          if (d.free_mask) {
-            // 32 / V lanes form one 32-bit word; OR their bits together.
-            constexpr int LPW = 32 / V;
-            uint32_t w = any ? (bits << (uint32_t)((e0 & 31))) : 0u;
-#pragma unroll
-            for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
-            if (any && (lane % LPW) == 0) {
-              const int64_t wi = e0 >> 5;
-              const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
-              if (whole) d.free_mask[wi] = w;
-              else atomicOr(&d.free_mask[wi], w);
-            }
-          }
-        }
-        block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
+        });
       }
+      block_to_part<8>(acc, nv, maxmask, sh.red, pb, tile);
     }
-    if (ph == PH_PGD_R) { nv = 8; maxmask = 1ull << 6; }
-    else if (ph == PH_ZERO) { nv = 6; maxmask = 1ull << 2; }
-    else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
-    else { nv = 4; maxmask = 0; }
-
-    if (!grid_barrier(d.bar, (uint32_t)G, target, &sh.abort_flag)) break;
-    reduce_tiles(pb, nv, maxmask, d.tile_base, d.nseg, sh.tot);
-
-    // ---------------- control (identical in every workgroup)
-    if (ph == PH_PGD_R) {
+    trace_put(d, pass_no, 1, clk());
+    trace_wg(d, pass_no, t_pass0, clk());
+    if (grid_reduce(d, d.epoch0 + (uint64_t)pass_no + 1, pb, nv, maxmask, d.nseg, sh.tot, &sh.abort_flag, pass_no)) {
       if (tid == 0) {
         double v[7] = {0, 0, 0, 0, 0, 0, -INFINITY};
         for (int s = 0; s < d.nseg; ++s) {
@@ -647,7 +674,264 @@ __global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
       for (int s = tid; s < d.nseg; s += BLOCK) sh.bs[s] = d.b[s] + sh.tot[s * 8 + 7];
       __syncthreads();
       if (tid == 0) sh.phase = PH_ZERO;
-    } else if (ph == PH_ZERO) {
+      trace_put(d, pass_no, 5, clk());
+    } else {
+      if (tid == 0) sh.phase = PH_DONE;
+    }
+    __syncthreads();
+    ++pass_no;
+    buf ^= 1;
+  }
+
+  // Register residency: the first tile of this workgroup keeps its y (pgd:
+  // rho~) and a slots in registers across passes when it has at most RS
+  // vector slots per thread; later passes then read no memory for it.
+  constexpr int RS = 4;
+  T ry[RS][V], ra[RS][V];
+  bool resident = false;
+  uint32_t rbits = 0u;      // element-validity masks of the resident slots, V bits each
+  // slot geometry of resident slot k
+  auto rslot = [&](const TileGeom& g, int k, int64_t& e0, bool& full, uint32_t& mask) __attribute__((always_inline)) {
+    e0 = 0; full = false; mask = 0u;
+    if (k < g.nsweep) slot<T>(g, k, e0, full, mask);
+  };
+  auto rmask = [&](int k) __attribute__((always_inline)) -> uint32_t { return (rbits >> (k * V)) & ((1u << V) - 1u); };
+
+  // free-mask bits of one vector slot: 32 / V lanes form one 32-bit word
+  auto put_mask = [&](bool any, int64_t e0, uint32_t bits, const TileGeom& g) __attribute__((always_inline)) {
+    constexpr int LPW = 32 / V;
+    uint32_t w = any ? (bits << (uint32_t)(e0 & 31)) : 0u;
+#pragma unroll
+    for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
+    // the host zeroed the mask: only words with set bits are written
+    if (w != 0u && ((tid & 63) % LPW) == 0) {
+      const int64_t wi = e0 >> 5;
+      const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
+      if (whole) d.free_mask[wi] = w;
+      else atomicOr(&d.free_mask[wi], w);
+    }
+  };
+
+  for (;;) {
+    if (sh.phase == PH_DONE) break;
+    const int ph = sh.phase;
+    double* pb = d.part + (size_t)buf * VMAX * TILES_PAD;
+    const uint64_t t_pass0 = clk();
+    trace_put(d, pass_no, 0, ((uint64_t)ph << 56) | (t_pass0 & 0x00ffffffffffffffull));
+    int nv = 0;
+    uint64_t maxmask = 0;
+
+    for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
+      const TileGeom g = tile_geom<T>(d, tile);
+      const int s = g.seg;
+      if (ph == PH_ZERO) {
+        nv = 6; maxmask = 1ull << 2;
+        double acc[6] = {0, 0, -INFINITY, 0, 0, 0};
+        // lam = 0: a.clip(y), slope, largest breakpoint, saturated sum, sum |a|, non-finite count
+        auto zero_elem = [&](double y, double av) __attribute__((always_inline)) {
+          const double x0 = clampd(y, lo, hi);
+          acc[0] = fma(av, x0, acc[0]);
+          if (y >= lo && y <= hi) acc[1] = fma(av, av, acc[1]);
+          if (av != 0.0) {
+            const double bp = (av > 0.0) ? (y - lo) / av : (y - hi) / av;
+            acc[2] = fmax(acc[2], bp);
+            acc[3] += (av > 0.0) ? av * lo : av * hi;
+          }
+          acc[4] += fabs(av);
+          if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
+        };
+        if (tile == (int)blockIdx.x && g.nsweep <= RS) {
+          // load (pgd: form) this workgroup's first tile into registers
+          const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+#pragma unroll
+          for (int k = 0; k < RS; ++k) {
+            int64_t e0; bool full; uint32_t mask;
+            rslot(g, k, e0, full, mask);
+            if (!mask) continue;
+            ld_vec<T>(A, e0, d.n, full, ra[k]);
+            if (!d.pgd) ld_vec<T>(Y, e0, d.n, full, ry[k]);
+          }
+          if (d.pgd) {
+            // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t
+            // in the stream precision; rho~ stays in registers.
+#pragma unroll
+            for (int k = 0; k < RS; ++k) {
+              int64_t e0; bool full; uint32_t mask;
+              rslot(g, k, e0, full, mask);
+              if (!mask) continue;
+              T rr[V], rg[V], rd[V], dn[V];
+              ld_vec<T>((const T*)d.rho, e0, d.n, full, rr);
+              ld_vec<T>((const T*)d.grad, e0, d.n, full, rg);
+              if (!d.zero_step) ld_vec<T>((const T*)d.dir, e0, d.n, full, rd);
+#pragma unroll
+              for (int q = 0; q < V; ++q) {
+                const double dd = d.zero_step ? -f64(rg[q]) : fma(beta, f64(rd[q]), -f64(rg[q]));
+                dn[q] = (T)dd;
+                ry[k][q] = (T)fma(step, dd, f64(rr[q]));
+              }
+              st_vec<T>((T*)d.dir, e0, mask, full, dn);
+            }
+          }
+          rbits = 0u;
+#pragma unroll
+          for (int k = 0; k < RS; ++k) {
+            int64_t e0; bool full; uint32_t mask;
+            rslot(g, k, e0, full, mask);
+            rbits |= mask << (k * V);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              // elements outside the segment contribute exactly zero from here on
+              if (!(mask & (1u << q))) { ra[k][q] = (T)0; ry[k][q] = (T)0; }
+              else zero_elem(f64(ry[k][q]), f64(ra[k][q]));
+            }
+          }
+          resident = true;
+        } else if (d.pgd) {
+          // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t,
+          // materialized in the stream precision (it is the point projected).
+          T* Dw = (T*)d.dir;
+          const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+          auto body = [&](const T* a, const T* r, const T* gr, const T* dp, int64_t e0, uint32_t mask, bool full)
+              __attribute__((always_inline)) {
+            T dn[V], rt[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              const double dd = dp ? fma(beta, f64(dp[q]), -f64(gr[q])) : -f64(gr[q]);
+              dn[q] = (T)dd;
+              rt[q] = (T)fma(step, dd, f64(r[q]));
+            }
+            st_vec<T>(Dw, e0, mask, full, dn);
+            st_vec<T>(X, e0, mask, full, rt);
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+              if (mask & (1u << q)) zero_elem(f64(rt[q]), f64(a[q]));
+          };
+          if (d.zero_step) {
+            const T* ptr[3] = {A, (const T*)d.rho, (const T*)d.grad};
+            stream_tile<T, 3, 1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+              body(b[0], b[1], b[2], nullptr, e0, mask, full);
+            });
+          } else {
+            const T* ptr[4] = {A, (const T*)d.rho, (const T*)d.grad, (const T*)d.dir};
+            stream_tile<T, 4, 1>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+              body(b[0], b[1], b[2], b[3], e0, mask, full);
+            });
+          }
+        } else {
+          const T* ptr[2] = {Y, A};
+          stream_tile<T, 2, 2>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+              if (mask & (1u << q)) zero_elem(f64(b[0][q]), f64(b[1][q]));
+          });
+        }
+        block_to_part<6>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_SEARCH) {
+        nv = 2 * NT; maxmask = 0;
+        if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
+        double acc[2 * NT] = {0, 0, 0, 0};
+        const double l0 = sh.S.trial[s][0], l1 = sh.S.trial[s][1];
+        // phi(lam_t) + b = a.clip(y - lam_t a) and its slope sum_free a^2, per trial;
+        // elements outside the segment enter with a = 0, y = 0 and add nothing
+        auto run = [&](auto two_c) __attribute__((always_inline)) {
+          constexpr bool TWO = decltype(two_c)::value;
+          auto elem = [&](double yq, double av) __attribute__((always_inline)) {
+            const double a2 = av * av;
+            const double z0 = fma(-l0, av, yq);
+            const double x0 = fmin(fmax(z0, lo), hi);
+            acc[0] = fma(av, x0, acc[0]);
+            acc[1] += (x0 == z0) ? a2 : 0.0;          // free: the clip left z unchanged
+            if constexpr (TWO) {
+              const double z1 = fma(-l1, av, yq);
+              const double x1 = fmin(fmax(z1, lo), hi);
+              acc[2] = fma(av, x1, acc[2]);
+              acc[3] += (x1 == z1) ? a2 : 0.0;
+            }
+          };
+          if (tile == (int)blockIdx.x && resident) {
+#pragma unroll
+            for (int k = 0; k < RS; ++k)
+#pragma unroll
+              for (int q = 0; q < V; ++q) elem(f64(ry[k][q]), f64(ra[k][q]));
+          } else {
+            const T* ptr[2] = {Y, A};
+            stream_tile<T, 2, 2>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+#pragma unroll
+              for (int q = 0; q < V; ++q) {
+                const bool ok = (mask >> q) & 1u;
+                elem(ok ? f64(b[0][q]) : 0.0, ok ? f64(b[1][q]) : 0.0);
+              }
+            });
+          }
+        };
+        if (l1 == l1) run(std::true_type{}); else run(std::false_type{});
+        block_to_part<2 * NT>(acc, nv, maxmask, sh.red, pb, tile);
+      } else {  // PH_FINAL
+        nv = 4; maxmask = 0;
+        double acc[4] = {0, 0, 0, 0};
+        const double lam = sh.S.lam[s];
+        const T* R = (const T*)d.rho;
+        // x = clip(y - lam a) in the stream precision; a.x, free count, pgd norms
+        auto final_slot = [&](const T* yv, const T* a, int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) -> uint32_t {
+          uint32_t bits = 0;
+          T r[V];
+          if (d.pgd) ld_vec<T>(R, e0, d.n, full, r);
+          T xo[V];
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            const double z = fma(-lam, f64(a[q]), f64(yv[q]));
+            xo[q] = (T)clampd(z, lo, hi);
+            if (!(mask & (1u << q))) continue;
+            const double xr = (double)xo[q];
+            acc[0] = fma(f64(a[q]), xr, acc[0]);
+            if (z >= lo && z <= hi) { acc[1] += 1.0; bits |= 1u << q; }
+            if (d.pgd) {
+              const double df = xr - f64(r[q]);
+              acc[2] = fma(df, df, acc[2]);
+              acc[3] = fma(xr, xr, acc[3]);
+            }
+          }
+          st_vec<T>(X, e0, mask, full, xo);
+          return bits;
+        };
+        if (tile == (int)blockIdx.x && resident) {
+#pragma unroll
+          for (int k = 0; k < RS; ++k) {
+            int64_t e0; bool full; uint32_t mask;
+            rslot(g, k, e0, full, mask);
+            mask = rmask(k);
+            const bool any = mask != 0u;
+            const uint32_t bits = any ? final_slot(ry[k], ra[k], e0, mask, full) : 0u;
+            if (d.free_mask) put_mask(any, e0, bits, g);
+          }
+        } else {
+          for (int k = 0; k < g.nsweep; ++k) {
+            int64_t e0; bool full; uint32_t mask;
+            const bool any = slot<T>(g, k, e0, full, mask);
+            uint32_t bits = 0;
+            if (any) {
+              T yv[V], a[V];
+              ld_vec<T>(Y, e0, d.n, full, yv);
+              ld_vec<T>(A, e0, d.n, full, a);
+              bits = final_slot(yv, a, e0, mask, full);
+            }
+            if (d.free_mask) put_mask(any, e0, bits, g);
+          }
+        }
+        block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
+      }
+    }
+    if (ph == PH_ZERO) { nv = 6; maxmask = 1ull << 2; }
+    else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
+    else { nv = 4; maxmask = 0; }
+
+    trace_put(d, pass_no, 1, clk());
+    trace_wg(d, pass_no, t_pass0, clk());
+    if (!grid_reduce(d, d.epoch0 + (uint64_t)pass_no + 1, pb, nv, maxmask, d.nseg, sh.tot, &sh.abort_flag, pass_no)) break;
+    trace_put(d, pass_no, 4, clk());
+
+    // ---------------- control (identical in every workgroup)
+    if (ph == PH_ZERO) {
       for (int s = tid; s < d.nseg; s += BLOCK) {
         const double* t = &sh.tot[s * 6];
         double scale = t[4] * fmax(fabs(lo), fabs(hi));
@@ -656,7 +940,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
           sh.S.lam[s] = 0.0; sh.S.outcome[s] = PGDTO_NONFINITE; sh.S.state[s] = SEG_DONE;
           sh.S.npass[s] = 0; sh.S.width[s] = 0.0; sh.S.scale[s] = scale;
         } else {
-          search_init(sh.S, s, t[0] - sh.bs[s], t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search);
+          search_init(sh.S, s, t[0] - sh.bs[s], t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search, true);
         }
       }
       __syncthreads();
@@ -670,7 +954,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
       for (int s = tid; s < d.nseg; s += BLOCK) {
         if (sh.S.state[s] != SEG_SEARCH) continue;
         search_update(sh.S, s, sh.tot[s * 4 + 0], sh.tot[s * 4 + 2], sh.tot[s * 4 + 1], sh.tot[s * 4 + 3],
-                      sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search);
+                      sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search, true);
       }
       __syncthreads();
       if (tid == 0) {
@@ -724,12 +1008,14 @@ __global__ __launch_bounds__(BLOCK) void k_solve_1d(const Desc d) {
       if (tid == 0) sh.phase = PH_DONE;
     }
     __syncthreads();
+    trace_put(d, pass_no, 5, clk());
+    ++pass_no;
     buf ^= 1;
     if (sh.phase == PH_DONE) break;
   }
   int32_t* errp = nullptr;
   if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
-  kernel_exit(d.bar, (uint32_t)G, errp);
+  report_error(d, errp);
 }
 
 // ================================================================== coupled kernel
@@ -747,6 +1033,7 @@ template <int M> struct CN {
   static constexpr int NV_NEWTON = M + NJ;
   static constexpr int NV_CHECK = M * M + (FUSE ? NV_NEWTON : 0);
   static constexpr int NV_FINAL = M + 3;
+  static constexpr int U = (M <= 2) ? 4 : 2;     // vector slots in flight per chunk
   static constexpr int NVM = NV_CHECK > NV_ZERO ? (NV_CHECK > NV_S1 ? NV_CHECK : NV_S1) : (NV_ZERO > NV_S1 ? NV_ZERO : NV_S1);
 };
 
@@ -763,7 +1050,7 @@ struct NewtonState {
 
 struct ShC {
   double tot[VMAX];
-  double red[NWAVE * VMAX];
+  double red[NWAVE * BLOCK];
   double bs[PGDTO_MAX_M];
   Search S;
   NewtonState N;
@@ -979,13 +1266,16 @@ __device__ int newton_after_trial(ShC& sh) {
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
+__global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
   constexpr int V = VT<T>::N;
   using C = CN<M>;
   __shared__ ShC sh;
+  __shared__ Desc sd;
+  load_desc(sd);
+  const Desc& d = sd;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
-  const double lo = d.lo, hi = d.hi, kappa = d.kappa;
+  const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi), kappa = d.kappa;
 
   if (tid == 0) {
     sh.phase = d.pgd ? PH_PGD_R : PH_ZERO;
@@ -1007,18 +1297,24 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
   }
   __syncthreads();
 
-  uint32_t target = 0;
   int buf = 0;
   const T* Arow[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) Arow[j] = (const T*)d.A + (int64_t)j * d.lda;
   T* X = (T*)d.x;
   const T* Y = d.pgd ? (const T*)d.x : (const T*)d.y;
+  const T* sptr[M + 1];
+  sptr[0] = Y;
+#pragma unroll
+  for (int j = 0; j < M; ++j) sptr[1 + j] = Arow[j];
   int ls_total = 0;
 
+  int pass_no = 0;
   for (;;) {
     const int ph = sh.phase;
     double* pb = d.part + (size_t)buf * VMAX * TILES_PAD;
+    const uint64_t t_pass0 = clk();
+    trace_put(d, pass_no, 0, ((uint64_t)ph << 56) | (t_pass0 & 0x00ffffffffffffffull));
     int nv;
     uint64_t maxmask = 0;
     switch (ph) {
@@ -1132,88 +1428,102 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
             lt[j][t] = sh.S.trial[j][t];
             on[j][t] = (sh.S.state[j] == SEG_SEARCH) && (lt[j][t] == lt[j][t]);
           }
-        for (int k = 0; k < g.nsweep; ++k) {
-          int64_t e0; bool full; uint32_t mask;
-          if (!slot<T>(g, k, e0, full, mask)) continue;
-          T yv[V], a[M][V];
-          ld_vec<T>(Y, e0, d.n, full, yv);
-#pragma unroll
-          for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+        // row j alone at its trial lam_jt: a_j.clip(y - lam_jt a_j) and the slope sum_free a_j^2
+        stream_tile<T, M + 1, C::U>(g, d.n, sptr, [&](const T (&b)[M + 1][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
+            const double yq = f64(b[0][q]);
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-              const double av = f64(a[j][q]);
+              const double av = f64(b[1 + j][q]);
 #pragma unroll
               for (int t = 0; t < NT; ++t) {
                 if (!on[j][t]) continue;
-                const double z = fma(-lt[j][t], av, f64(yv[q]));
+                const double z = fma(-lt[j][t], av, yq);
                 acc[(j * NT + t) * 2] = fma(av, clampd(z, lo, hi), acc[(j * NT + t) * 2]);
                 if (z >= lo && z <= hi) acc[(j * NT + t) * 2 + 1] = fma(av, av, acc[(j * NT + t) * 2 + 1]);
               }
             }
           }
-        }
+        });
         block_to_part<C::NV_S1>(acc, nv, maxmask, sh.red, pb, tile);
-      } else if (ph == PH_CHECK || ph == PH_NEWTON) {
-        // PH_NEWTON: h and the upper triangle of A D A^T at the trial point.
-        // PH_CHECK: candidate sums a_k.x(lam_j* e_j) (+ the Newton sums at lam0).
-        constexpr int NVC = C::NV_CHECK > C::NV_NEWTON ? C::NV_CHECK : C::NV_NEWTON;
-        double acc[NVC];
+      } else if (ph == PH_NEWTON) {
+        // h and the upper triangle of A D A^T at the trial multiplier
+        double acc[C::NV_NEWTON];
 #pragma unroll
-        for (int v = 0; v < NVC; ++v) acc[v] = 0.0;
-        const bool check = (ph == PH_CHECK);
-        const bool newton = (ph == PH_NEWTON) || C::FUSE;
-        const int nbase = check ? M * M : 0;
-        double lamv[M], cand[M];
-        bool con[M];
+        for (int v = 0; v < C::NV_NEWTON; ++v) acc[v] = 0.0;
+        double lamv[M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-          lamv[j] = check ? sh.N.lam1[j] : sh.N.trial[j];
-          cand[j] = sh.N.lam1[j];
-          con[j] = check && (cand[j] > 0.0);
-        }
-        for (int k = 0; k < g.nsweep; ++k) {
-          int64_t e0; bool full; uint32_t mask;
-          if (!slot<T>(g, k, e0, full, mask)) continue;
-          T yv[V], a[M][V];
-          ld_vec<T>(Y, e0, d.n, full, yv);
-#pragma unroll
-          for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
+        for (int j = 0; j < M; ++j) lamv[j] = sh.N.trial[j];
+        stream_tile<T, M + 1, C::U>(g, d.n, sptr, [&](const T (&b)[M + 1][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
-            if (check) {
+            double z = f64(b[0][q]);
 #pragma unroll
-              for (int j = 0; j < M; ++j) {
-                if (!con[j]) continue;
-                const double xc = clampd(fma(-cand[j], f64(a[j][q]), f64(yv[q])), lo, hi);
+            for (int j = 0; j < M; ++j) z = fma(-lamv[j], f64(b[1 + j][q]), z);
+            const double x = clampd(z, lo, hi);
+            const bool fr = (z >= lo && z <= hi);
+            double fa[M];
 #pragma unroll
-                for (int kk = 0; kk < M; ++kk) acc[j * M + kk] = fma(f64(a[kk][q]), xc, acc[j * M + kk]);
-              }
+            for (int j = 0; j < M; ++j) {
+              acc[j] = fma(f64(b[1 + j][q]), x, acc[j]);
+              fa[j] = fr ? f64(b[1 + j][q]) : 0.0;
             }
-            if (newton) {
-              double z = f64(yv[q]);
+            int p = M;
 #pragma unroll
-              for (int j = 0; j < M; ++j) z = fma(-lamv[j], f64(a[j][q]), z);
+            for (int j = 0; j < M; ++j)
+#pragma unroll
+              for (int kk = j; kk < M; ++kk) { acc[p] = fma(fa[j], f64(b[1 + kk][q]), acc[p]); ++p; }
+          }
+        });
+        block_to_part<C::NV_NEWTON>(acc, nv, maxmask, sh.red, pb, tile);
+      } else if (ph == PH_CHECK) {
+        // candidate sums a_k.x(lam_j* e_j) (+ the Newton sums at lam0 when fused)
+        double acc[C::NV_CHECK];
+#pragma unroll
+        for (int v = 0; v < C::NV_CHECK; ++v) acc[v] = 0.0;
+        double cand[M];
+        bool con[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          cand[j] = sh.N.lam1[j];
+          con[j] = cand[j] > 0.0;
+        }
+        stream_tile<T, M + 1, C::U>(g, d.n, sptr, [&](const T (&b)[M + 1][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            if (!(mask & (1u << q))) continue;
+            const double yq = f64(b[0][q]);
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              if (!con[j]) continue;
+              const double xc = clampd(fma(-cand[j], f64(b[1 + j][q]), yq), lo, hi);
+#pragma unroll
+              for (int kk = 0; kk < M; ++kk) acc[j * M + kk] = fma(f64(b[1 + kk][q]), xc, acc[j * M + kk]);
+            }
+            if constexpr (C::FUSE) {
+              double z = yq;
+#pragma unroll
+              for (int j = 0; j < M; ++j) z = fma(-cand[j], f64(b[1 + j][q]), z);
               const double x = clampd(z, lo, hi);
               const bool fr = (z >= lo && z <= hi);
               double fa[M];
 #pragma unroll
               for (int j = 0; j < M; ++j) {
-                acc[nbase + j] = fma(f64(a[j][q]), x, acc[nbase + j]);
-                fa[j] = fr ? f64(a[j][q]) : 0.0;
+                acc[M * M + j] = fma(f64(b[1 + j][q]), x, acc[M * M + j]);
+                fa[j] = fr ? f64(b[1 + j][q]) : 0.0;
               }
-              int p = nbase + M;
+              int p = M * M + M;
 #pragma unroll
               for (int j = 0; j < M; ++j)
 #pragma unroll
-                for (int kk = j; kk < M; ++kk) { acc[p] = fma(fa[j], f64(a[kk][q]), acc[p]); ++p; }
+                for (int kk = j; kk < M; ++kk) { acc[p] = fma(fa[j], f64(b[1 + kk][q]), acc[p]); ++p; }
             }
           }
-        }
-        block_to_part<NVC>(acc, nv, maxmask, sh.red, pb, tile);
+        });
+        block_to_part<C::NV_CHECK>(acc, nv, maxmask, sh.red, pb, tile);
       } else {  // PH_FINAL
         double acc[C::NV_FINAL];
 #pragma unroll
@@ -1258,7 +1568,8 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
             uint32_t w = any ? (bits << (uint32_t)(e0 & 31)) : 0u;
 #pragma unroll
             for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
-            if (any && (lane % LPW) == 0) {
+            // the host zeroed the mask: only words with set bits are written
+            if (w != 0u && (lane % LPW) == 0) {
               const int64_t wi = e0 >> 5;
               const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
               if (whole) d.free_mask[wi] = w;
@@ -1270,8 +1581,10 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
       }
     }
 
-    if (!grid_barrier(d.bar, (uint32_t)G, target, &sh.abort_flag)) break;
-    reduce_tiles(pb, nv, maxmask, d.tile_base, 1, sh.tot);
+    trace_put(d, pass_no, 1, clk());
+    trace_wg(d, pass_no, t_pass0, clk());
+    if (!grid_reduce(d, d.epoch0 + (uint64_t)pass_no + 1, pb, nv, maxmask, 1, sh.tot, &sh.abort_flag, pass_no)) break;
+    trace_put(d, pass_no, 4, clk());
 
     // ---------------- control (identical in every workgroup)
     const double* t = sh.tot;
@@ -1292,7 +1605,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
         sh.S.ssat[j] = t[3 * M + j];
         if (d.stage1 && t[5 * M] == 0.0) {
           search_init(sh.S, j, t[j] - sh.bs[j], t[M + j] + kappa, t[2 * M + j], t[3 * M + j], sh.bs[j], kappa,
-                      scale, d.search);
+                      scale, d.search, false);
         } else {
           sh.S.state[j] = SEG_DONE; sh.S.lam[j] = 0.0; sh.S.npass[j] = 0;
         }
@@ -1326,7 +1639,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
       if (tid < M && sh.S.state[tid] == SEG_SEARCH) {
         const int j = tid;
         search_update(sh.S, j, t[(j * NT + 0) * 2], t[(j * NT + 1) * 2], t[(j * NT + 0) * 2 + 1],
-                      t[(j * NT + 1) * 2 + 1], sh.bs[j], kappa, d.tol_n, d.tol_b, d.max_search, d.search);
+                      t[(j * NT + 1) * 2 + 1], sh.bs[j], kappa, d.tol_n, d.tol_b, d.max_search, d.search, false);
       }
       __syncthreads();
       if (tid == 0) {
@@ -1428,23 +1741,21 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc d) {
       if (tid == 0) sh.phase = PH_DONE;
     }
     __syncthreads();
+    trace_put(d, pass_no, 5, clk());
+    ++pass_no;
     buf ^= 1;
     if (sh.phase == PH_DONE) break;
   }
   int32_t* errp = nullptr;
   if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
-  kernel_exit(d.bar, (uint32_t)G, errp);
+  report_error(d, errp);
 }
 
-// Marks a result as failed and clears the barrier words (used by the host
-// after a failed launch).
-__global__ void k_mark_error(uint32_t* bar, void* result, int is_pgd) {
-  if (threadIdx.x == 0) {
-    bar[0] = 0; bar[1] = 0; bar[2] = 0;
-    if (result) {
-      pgdto_result* R = is_pgd ? &((pgdto_pgd_out*)result)->proj : (pgdto_result*)result;
-      R->error = PGDTO_ERR_HIP;
-    }
+// Marks a result as failed (used by the host after a failed launch).
+__global__ void k_mark_error(void* result, int is_pgd) {
+  if (threadIdx.x == 0 && result) {
+    pgdto_result* R = is_pgd ? &((pgdto_pgd_out*)result)->proj : (pgdto_result*)result;
+    R->error = PGDTO_ERR_HIP;
   }
 }
 
@@ -1484,8 +1795,8 @@ hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooper
   return hipLaunchKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
 }
 
-hipError_t launch_mark_error(uint32_t* bar, void* result, int is_pgd, hipStream_t stream) {
-  hipLaunchKernelGGL(k_mark_error, dim3(1), dim3(64), 0, stream, bar, result, is_pgd);
+hipError_t launch_mark_error(void* result, int is_pgd, hipStream_t stream) {
+  hipLaunchKernelGGL(k_mark_error, dim3(1), dim3(64), 0, stream, result, is_pgd);
   return hipGetLastError();
 }
 
