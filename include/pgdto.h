@@ -248,7 +248,10 @@ int pgdto_version(void);
  * left, control done; the last workgroup's loop done and totals seen.  This
  * copies up to max_records records (8 values each) of the last launch to host
  * memory `out` and clears them; returns the number of records copied
- * (0 when tracing is off) or a negative status. */
+ * (0 when tracing is off) or a negative status.  With max_records < 0 it
+ * instead copies the per-workgroup table of the first 16 passes, 16 x 1024 x 4
+ * values (loop start, loop end, wait end, HW_ID | XCC_ID << 32), into `out`
+ * (65536 values) and returns 16. */
 int pgdto_trace_read(pgdto_ctx* ctx, uint64_t* out, int max_records);
 
 /* Layout introspection for language bindings: sizeof of the public structs.

@@ -69,9 +69,9 @@ extern "C" int pgdto_version(void) { return PGDTO_VERSION; }
 extern "C" int pgdto_trace_read(pgdto_ctx* c, uint64_t* out, int max_records) {
   if (!c || !out) return PGDTO_ERR_ARG;
   if (!c->trace) return 0;
-  if (max_records < 0) {   // per-workgroup table: TRACE_WG_PASSES x 1024 x (start, end)
+  if (max_records < 0) {   // per-workgroup table: TRACE_WG_PASSES x GMAX x TRACE_WG_W
     if (hipDeviceSynchronize() != hipSuccess) return PGDTO_ERR_HIP;
-    if (hipMemcpy(out, c->trace + (size_t)TRACE_MAX * TRACE_W, sizeof(uint64_t) * TRACE_WG_PASSES * 1024 * 2,
+    if (hipMemcpy(out, c->trace + (size_t)TRACE_MAX * TRACE_W, sizeof(uint64_t) * TRACE_WG_PASSES * GMAX * TRACE_WG_W,
                   hipMemcpyDeviceToHost) != hipSuccess) return PGDTO_ERR_HIP;
     return TRACE_WG_PASSES;
   }

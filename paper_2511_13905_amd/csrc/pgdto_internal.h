@@ -18,7 +18,9 @@ constexpr int VMAX = 112;                  // partial values per tile (coupled, 
 constexpr int PART_DOUBLES = 2 * VMAX * TILES_PAD;   // double-buffered
 constexpr int GMAX = 1024;                 // workgroups of one launch (upper bound)
 constexpr int TOT_MAX = 1024;              // per-segment totals of one pass
-constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + 16 + 16 + TOT_MAX;   // uint64 words
+constexpr int NREP = 64;                   // copies of the go word, each with the totals beside it
+constexpr int REP_WORDS = 128;             // 1 KiB per copy: go word + up to 127 totals
+constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + (size_t)NREP * REP_WORDS + 16 + TOT_MAX;   // uint64 words
 
 // Bounded spin of the grid barrier: about a second of waiting before the
 // workgroup gives up, flags PGDTO_ERR_TIMEOUT and leaves the kernel.
@@ -63,8 +65,9 @@ struct Desc {
 // [6] loop done, [7] saw the totals.
 constexpr int TRACE_MAX = 128;
 constexpr int TRACE_W = 8;
-constexpr int TRACE_WG_PASSES = 16;        // per-workgroup loop times kept for the first passes
-constexpr size_t TRACE_WORDS = (size_t)TRACE_MAX * TRACE_W + (size_t)TRACE_WG_PASSES * 1024 * 2;
+constexpr int TRACE_WG_PASSES = 16;        // per-workgroup records kept for the first passes
+constexpr int TRACE_WG_W = 4;              // words per workgroup record
+constexpr size_t TRACE_WORDS = (size_t)TRACE_MAX * TRACE_W + (size_t)TRACE_WG_PASSES * GMAX * TRACE_WG_W;
 
 // Tiling: the tile size depends only on n and the dtype, so that an
 // instance's reduction order (and hence its bits) does not depend on how many

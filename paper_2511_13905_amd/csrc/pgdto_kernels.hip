@@ -150,7 +150,7 @@ __device__ __forceinline__ void block_to_part(const double (&acc)[NV], int nv, u
 // workgroup runs this on the same data in the same order.
 __device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const int32_t* tile_base,
                              int nseg, double* tot) {
-  constexpr int LMAX = 6;               // loads in flight per thread
+  constexpr int LMAX = 8;               // loads in flight per thread
   const int pairs = nseg * nv;
   int P = 64;
   while (P > 1 && pairs * P > BLOCK) P >>= 1;
@@ -192,11 +192,24 @@ __device__ __forceinline__ uint64_t clk() { return __builtin_amdgcn_s_memrealtim
 __device__ __forceinline__ void trace_put(const Desc& d, int pass, int slot, uint64_t v) {
   if (d.trace && blockIdx.x == 0 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
 }
-// per-workgroup (loop start, loop end) of each pass, after the per-pass records
+// per-workgroup records of each pass, after the per-pass records: loop start,
+// loop end, go seen (end of the pass's wait), hardware ids (HW_ID | XCC_ID << 32)
+__device__ __forceinline__ uint64_t* trace_wg_rec(const Desc& d, int pass) {
+  return d.trace + TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + blockIdx.x) * TRACE_WG_W;
+}
 __device__ __forceinline__ void trace_wg(const Desc& d, int pass, uint64_t t_start, uint64_t t_end) {
-  if (d.trace && threadIdx.x == 0 && pass < TRACE_WG_PASSES)
-    d.trace[TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + blockIdx.x) * 2 + 0] = t_start,
-    d.trace[TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + blockIdx.x) * 2 + 1] = t_end;
+  if (d.trace && threadIdx.x == 0 && pass < TRACE_WG_PASSES) {
+    uint64_t* r = trace_wg_rec(d, pass);
+    r[0] = t_start;
+    r[1] = t_end;
+    // HW_ID (hwreg 4, all 32 bits) and XCC_ID (hwreg 20, low 4 bits)
+    const uint32_t hw = __builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11));
+    const uint32_t xcc = __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11));
+    r[3] = (uint64_t)hw | ((uint64_t)xcc << 32);
+  }
+}
+__device__ __forceinline__ void trace_wg_go(const Desc& d, int pass, uint64_t t) {
+  if (d.trace && threadIdx.x == 0 && pass < TRACE_WG_PASSES) trace_wg_rec(d, pass)[2] = t;
 }
 // records of the last workgroup (slots 6, 7)
 __device__ __forceinline__ void trace_last(const Desc& d, int pass, int slot, uint64_t v) {
@@ -209,32 +222,37 @@ __device__ __forceinline__ void trace_last(const Desc& d, int pass, int slot, ui
 // own cache line (no shared counter: device-scope atomics on one address
 // serialise at the memory side and cost ~G x 70 ns).  Workgroup 0 waits for
 // all flags with all its threads, reduces the per-tile partials once (fixed
-// order), stores the totals and raises `go`; the other workgroups wait on
-// `go` and read the totals.  Every wait is bounded: on expiry the error word
-// records this launch's epoch and every workgroup leaves.
+// order), and publishes the totals and a go word in NREP copies 1 KiB apart;
+// every other workgroup polls and reads only its own copy, so that no single
+// line is polled by hundreds of workgroups (that queues the polls at one
+// memory channel and staggers the start of the next pass by microseconds).
+// Every wait is bounded: on expiry the error word records this launch's epoch
+// and every workgroup leaves.
 constexpr int FLAG_STRIDE = 16;     // uint64 per flag: one 128-byte line each
+constexpr int REP_VALS = REP_WORDS - 1;
 
 struct SyncWords {
   uint64_t* flags;   // [GMAX * FLAG_STRIDE]
-  uint64_t* go;      // one line
+  uint64_t* rep;     // [NREP * REP_WORDS]: go word, then totals (double) when they fit
   uint64_t* err;     // one line: epoch of the launch that timed out
-  double* totals;    // [TOT_MAX]
+  double* totals;    // [TOT_MAX], used when the totals do not fit a copy
 };
 
 __device__ __forceinline__ SyncWords sync_words(const Desc& d) {
   SyncWords w;
   w.flags = d.sync;
-  w.go = d.sync + (size_t)GMAX * FLAG_STRIDE;
-  w.err = w.go + FLAG_STRIDE;
+  w.rep = d.sync + (size_t)GMAX * FLAG_STRIDE;
+  w.err = w.rep + (size_t)NREP * REP_WORDS;
   w.totals = (double*)(w.err + FLAG_STRIDE);
   return w;
 }
 
-__device__ bool grid_reduce(const Desc& d, uint64_t epoch, const double* pb, int nv, uint64_t maxmask,
+__device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const double* pb, int nv, uint64_t maxmask,
                             int nseg, double* tot, int32_t* abort_flag, int pass_no) {
   const SyncWords W = sync_words(d);
   const int G = gridDim.x;
   const int ntot = nseg * nv;
+  const bool in_rep = ntot <= REP_VALS;
   __syncthreads();
   if (threadIdx.x == 0) {
     *abort_flag = 0;
@@ -261,23 +279,34 @@ __device__ bool grid_reduce(const Desc& d, uint64_t epoch, const double* pb, int
     trace_put(d, pass_no, 2, clk());
     reduce_tiles(pb, nv, maxmask, d.tile_base, nseg, tot);
     trace_put(d, pass_no, 3, clk());
-    for (int i = threadIdx.x; i < ntot; i += BLOCK) W.totals[i] = tot[i];
+    if (in_rep) {
+      for (int i = threadIdx.x; i < NREP * ntot; i += BLOCK) {
+        const int r = i / ntot, k = i - r * ntot;
+        ((double*)(W.rep + (size_t)r * REP_WORDS + 1))[k] = tot[k];
+      }
+    } else {
+      for (int i = threadIdx.x; i < ntot; i += BLOCK) W.totals[i] = tot[i];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(W.go, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // one wave raises every copy of the go word (one release for all of them)
+    if (threadIdx.x < 64) {
+      for (int r = threadIdx.x; r < NREP; r += 64)
+        __hip_atomic_store(W.rep + (size_t)r * REP_WORDS, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     return true;
   }
   trace_last(d, pass_no, 6, clk());
+  uint64_t* my = W.rep + (size_t)(blockIdx.x % NREP) * REP_WORDS;
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
     bool ok = true;
-    while (__hip_atomic_load(W.go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    while (__hip_atomic_load(my, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > SPIN_LIMIT || __hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == d.epoch0) {
         ok = false;
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!ok) {
       __hip_atomic_store(W.err, d.epoch0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       *abort_flag = 1;
@@ -286,7 +315,14 @@ __device__ bool grid_reduce(const Desc& d, uint64_t epoch, const double* pb, int
   __syncthreads();
   if (*abort_flag) return false;
   trace_last(d, pass_no, 7, clk());
-  for (int i = threadIdx.x; i < ntot; i += BLOCK) tot[i] = W.totals[i];
+  trace_wg_go(d, pass_no, clk());
+  // The totals are the only data of other workgroups read here: device-scope
+  // loads of them, issued after the go word was seen, return what workgroup 0
+  // wrote back before raising it.  No acquire fence: it would invalidate this
+  // XCD's whole L2 once per workgroup and pass.
+  uint64_t* src = in_rep ? my + 1 : (uint64_t*)W.totals;
+  for (int i = threadIdx.x; i < ntot; i += BLOCK)
+    tot[i] = __builtin_bit_cast(double, __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   __syncthreads();
   return true;
 }
@@ -754,15 +790,30 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
           if (d.pgd) {
             // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t
             // in the stream precision; rho~ stays in registers.
+            // the loads of slot k + 1 are issued before d_t of slot k is
+            // stored (the store may alias them)
+            T nr[V], ng[V], nd[V];
+            auto fetch = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+              for (int q = 0; q < V; ++q) nr[q] = ng[q] = nd[q] = (T)0;
+              if (k >= RS) return;
+              int64_t e0; bool full; uint32_t mask;
+              rslot(g, k, e0, full, mask);
+              if (!mask) return;
+              ld_vec<T>((const T*)d.rho, e0, d.n, full, nr);
+              ld_vec<T>((const T*)d.grad, e0, d.n, full, ng);
+              if (!d.zero_step) ld_vec<T>((const T*)d.dir, e0, d.n, full, nd);
+            };
+            fetch(0);
 #pragma unroll
             for (int k = 0; k < RS; ++k) {
+              T rr[V], rg[V], rd[V], dn[V];
+#pragma unroll
+              for (int q = 0; q < V; ++q) { rr[q] = nr[q]; rg[q] = ng[q]; rd[q] = nd[q]; }
+              fetch(k + 1);
               int64_t e0; bool full; uint32_t mask;
               rslot(g, k, e0, full, mask);
               if (!mask) continue;
-              T rr[V], rg[V], rd[V], dn[V];
-              ld_vec<T>((const T*)d.rho, e0, d.n, full, rr);
-              ld_vec<T>((const T*)d.grad, e0, d.n, full, rg);
-              if (!d.zero_step) ld_vec<T>((const T*)d.dir, e0, d.n, full, rd);
 #pragma unroll
               for (int q = 0; q < V; ++q) {
                 const double dd = d.zero_step ? -f64(rg[q]) : fma(beta, f64(rd[q]), -f64(rg[q]));
@@ -872,10 +923,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
         const double lam = sh.S.lam[s];
         const T* R = (const T*)d.rho;
         // x = clip(y - lam a) in the stream precision; a.x, free count, pgd norms
-        auto final_slot = [&](const T* yv, const T* a, int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) -> uint32_t {
+        auto final_slot = [&](const T* yv, const T* a, const T* r, int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) -> uint32_t {
           uint32_t bits = 0;
-          T r[V];
-          if (d.pgd) ld_vec<T>(R, e0, d.n, full, r);
           T xo[V];
 #pragma unroll
           for (int q = 0; q < V; ++q) {
@@ -895,26 +944,56 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
           return bits;
         };
         if (tile == (int)blockIdx.x && resident) {
+          // rho_t of slot k + 1 is requested before x of slot k is stored
+          // (the store may alias it), so the loads overlap the slot work
+          T rnext[V];
+          auto fetch_r = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) rnext[q] = (T)0;
+            if (d.pgd && k < RS && rmask(k)) {
+              int64_t e0; bool full; uint32_t mask;
+              rslot(g, k, e0, full, mask);
+              ld_vec<T>(R, e0, d.n, full, rnext);
+            }
+          };
+          fetch_r(0);
 #pragma unroll
           for (int k = 0; k < RS; ++k) {
+            T rcur[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) rcur[q] = rnext[q];
+            fetch_r(k + 1);
             int64_t e0; bool full; uint32_t mask;
             rslot(g, k, e0, full, mask);
             mask = rmask(k);
             const bool any = mask != 0u;
-            const uint32_t bits = any ? final_slot(ry[k], ra[k], e0, mask, full) : 0u;
+            const uint32_t bits = any ? final_slot(ry[k], ra[k], rcur, e0, mask, full) : 0u;
             if (d.free_mask) put_mask(any, e0, bits, g);
           }
         } else {
-          for (int k = 0; k < g.nsweep; ++k) {
-            int64_t e0; bool full; uint32_t mask;
-            const bool any = slot<T>(g, k, e0, full, mask);
-            uint32_t bits = 0;
-            if (any) {
-              T yv[V], a[V];
-              ld_vec<T>(Y, e0, d.n, full, yv);
-              ld_vec<T>(A, e0, d.n, full, a);
-              bits = final_slot(yv, a, e0, mask, full);
+          // one slot ahead: the loads of slot k + 1 are issued before the
+          // store of slot k (x may alias y)
+          T ny[V], na[V], nr[V];
+          int64_t ne0 = 0; bool nfull = false, nany = false; uint32_t nmask = 0u;
+          auto fetch = [&](int k) __attribute__((always_inline)) {
+            nany = (k < g.nsweep) && slot<T>(g, k, ne0, nfull, nmask);
+            if (!nany) { nmask = 0u; ne0 = 0; nfull = false; }
+#pragma unroll
+            for (int q = 0; q < V; ++q) nr[q] = (T)0;
+            if (nany) {
+              ld_vec<T>(Y, ne0, d.n, nfull, ny);
+              ld_vec<T>(A, ne0, d.n, nfull, na);
+              if (d.pgd) ld_vec<T>(R, ne0, d.n, nfull, nr);
             }
+          };
+          fetch(0);
+          for (int k = 0; k < g.nsweep; ++k) {
+            T yv[V], a[V], r[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) { yv[q] = ny[q]; a[q] = na[q]; r[q] = nr[q]; }
+            const int64_t e0 = ne0; const bool full = nfull, any = nany; const uint32_t mask = nmask;
+            fetch(k + 1);
+            const uint32_t bits = any ? final_slot(yv, a, r, e0, mask, full) : 0u;
             if (d.free_mask) put_mask(any, e0, bits, g);
           }
         }
