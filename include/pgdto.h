@@ -213,18 +213,33 @@ int pgdto_pgd_step(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_param
 int pgdto_pgd_step_async(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,
                          pgdto_pgd_out* out_dev, void* stream);
 
-/* Serving: continuous batching of projection requests. */
+/* Serving: continuous batching of projection requests.
+ *
+ * max_slots != 1 selects the persistent executor: one long-running
+ * cooperative launch whose workgroups form max_slots slots; each slot solves
+ * one request at a time and claims the next published request as soon as it
+ * finishes, so requests that arrive while others run are admitted as slots
+ * and budget free up, and requests of different sizes overlap on the device.
+ * Results are bitwise those of pgdto_project on the same problem.  The
+ * launch holds the GPU while requests are outstanding and ends a few ms
+ * after the last one; other launches on the device wait meanwhile.  The
+ * persistent executor takes float32 streams only (a float64 request fails
+ * with PGDTO_ERR_ARG).  max_slots == 1 selects the plain one-at-a-time path:
+ * FIFO, one full-GPU launch per request (any dtype). */
 typedef struct {
   size_t hbm_budget_bytes;   /* admission limit on the summed footprint of the
                                 requests in flight (0: 90% of free memory)    */
-  int32_t max_slots;         /* concurrent requests on the device (0: auto)   */
-  int32_t wg_per_slot;       /* workgroups per slot (0: auto)                 */
+  int32_t max_slots;         /* 1: plain path; 0: 8 slots; else slot count   */
+  int32_t wg_per_slot;       /* workgroups per slot (0: all that fit / slots) */
   int32_t queue_capacity;    /* pending requests (0: 65536)                   */
 } pgdto_batch_cfg;
 
 int pgdto_batch_create(pgdto_ctx* ctx, const pgdto_batch_cfg* cfg, pgdto_batch** out);
-/* Non-blocking.  The problem's device buffers must stay valid until poll
- * returns PGDTO_OK or an error for this ticket.  Host arrays are copied. */
+/* Non-blocking.  The problem's device buffers must hold their data when
+ * this is called (the executor may start on them at once, in no stream
+ * order: finish the work that writes y and A first) and stay valid until
+ * poll returns PGDTO_OK or an error for this ticket.  free_mask need not be
+ * cleared by the caller.  Host arrays are copied. */
 int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, const pgdto_params* params,
                        uint64_t* ticket);
 /* PGDTO_QUEUED / PGDTO_PENDING / PGDTO_OK (result copied, ticket retired) /
@@ -232,6 +247,12 @@ int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, const pgdto_pa
 int pgdto_batch_poll(pgdto_batch* b, uint64_t ticket, pgdto_result* out);
 /* Blocks until the ticket finishes (or errors). */
 int pgdto_batch_wait(pgdto_batch* b, uint64_t ticket, pgdto_result* out);
+/* pgdto_batch_poll (wait == 0) or pgdto_batch_wait (wait != 0) that also
+ * returns, when the ticket retires, times[0..2] = submitted, admitted to the
+ * device, completion seen, in ns on the host's monotonic clock. */
+int pgdto_batch_poll_timed(pgdto_batch* b, uint64_t ticket, pgdto_result* out, int64_t* times, int wait);
+/* Executor shape: slots and workgroups per slot (0, 0 on the plain path). */
+int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot);
 /* Statistics: admitted, completed, queued, in flight, peak footprint. */
 int pgdto_batch_stats(pgdto_batch* b, int64_t* admitted, int64_t* completed, int64_t* queued,
                       int64_t* in_flight, int64_t* peak_bytes);

@@ -105,6 +105,8 @@ SIGNATURES = {
     "pgdto_batch_submit": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_uint64)]),
     "pgdto_batch_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result)]),
     "pgdto_batch_wait": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result)]),
+    "pgdto_batch_poll_timed": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result), C.POINTER(C.c_int64), C.c_int]),
+    "pgdto_batch_shape": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pgdto_batch_stats": (C.c_int, [_VP] + [C.POINTER(C.c_int64)] * 5),
     "pgdto_batch_destroy": (C.c_int, [_VP]),
     "pgdto_status_string": (C.c_char_p, [C.c_int]),

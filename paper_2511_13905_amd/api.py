@@ -74,8 +74,9 @@ class _Keep:
 
 
 def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, free_mask=None,
-                   keep: _Keep | None = None):
-    """Fill a pgdto_problem from torch tensors; returns (struct, x, A_used)."""
+                   keep: _Keep | None = None, copy_ok: bool = True):
+    """Fill a pgdto_problem from torch tensors; returns (struct, x, A_used).
+    copy_ok=False: raise instead of copying A into 16-byte aligned rows."""
     keep = keep or _Keep()
     k = N.KINDS[kind] if isinstance(kind, str) else int(kind)
     if y is not None and not y.is_contiguous():
@@ -90,6 +91,9 @@ def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, 
         lda = n
     else:
         A_used = aligned_rows(A)
+        if not copy_ok and A_used.data_ptr() != A.data_ptr():
+            raise ValueError("A rows must start on 16-byte boundaries (stage them with aligned_rows() "
+                             "and finish that copy before submitting)")
         m = A_used.shape[0]
         lda = A_used.stride(0) if m > 1 else n
     if x is None:
@@ -225,3 +229,77 @@ def result_from_bytes(buf: torch.Tensor, pgd: bool = False) -> dict:
 
 def result_nbytes(pgd: bool = False) -> int:
     return C.sizeof(N.PgdOut if pgd else N.Result)
+
+
+class Batch:
+    """pgdto_batch: continuous batching of projection requests on one device.
+
+    max_slots=1 is the plain one-at-a-time path; otherwise the persistent
+    multi-slot executor (float32 streams).  submit() keeps the request's
+    tensors alive until the ticket retires; their data must be complete when
+    submit() is called (the executor starts at once, in no stream order), so
+    it never copies A: rows must already be 16-byte aligned (aligned_rows)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 0, wg_per_slot: int = 0,
+                 queue_capacity: int = 0):
+        cfg = N.BatchCfg()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.wg_per_slot = int(wg_per_slot)
+        cfg.queue_capacity = int(queue_capacity)
+        h = C.c_void_p()
+        _check(N.lib().pgdto_batch_create(ctx.h, C.byref(cfg), C.byref(h)), "pgdto_batch_create")
+        self.h = h
+        self.ctx = ctx
+        self._live = {}
+
+    def shape(self):
+        s, w = C.c_int32(), C.c_int32()
+        _check(N.lib().pgdto_batch_shape(self.h, C.byref(s), C.byref(w)), "pgdto_batch_shape")
+        return s.value, w.value
+
+    def submit(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None, params=None) -> int:
+        keep = _Keep()
+        s, x, A_used = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, copy_ok=False)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        t = C_u64()
+        _check(N.lib().pgdto_batch_submit(self.h, C_byref(s), C_byref(p), C_byref(t)), "pgdto_batch_submit")
+        self._live[t.value] = (y, A_used, x, free_mask)
+        return t.value
+
+    def x_of(self, ticket):
+        return self._live[ticket][2]
+
+    def poll(self, ticket, wait=False):
+        """(status, result dict or None, (t_submit, t_start, t_done) ns or None)."""
+        r = N.Result()
+        times = (C.c_int64 * 3)()
+        st = N.lib().pgdto_batch_poll_timed(self.h, ticket, C_byref(r), times, 1 if wait else 0)
+        if st in (N.QUEUED, N.PENDING):
+            return st, None, None
+        self._live.pop(ticket, None)
+        return st, r.to_dict(), (times[0], times[1], times[2])
+
+    def wait(self, ticket):
+        return self.poll(ticket, wait=True)
+
+    def stats(self):
+        v = [C.c_int64() for _ in range(5)]
+        _check(N.lib().pgdto_batch_stats(self.h, *[C.byref(x) for x in v]), "pgdto_batch_stats")
+        return dict(zip(["admitted", "completed", "queued", "in_flight", "peak_bytes"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().pgdto_batch_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def C_u64():
+    return C.c_uint64()

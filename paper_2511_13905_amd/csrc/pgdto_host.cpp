@@ -266,6 +266,8 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   d.pgd = is_pgd ? 1 : 0;
   const int grid = grid_for(c, d);
   if (grid <= 0) return PGDTO_ERR_HIP;
+  d.wg_base = 0;
+  d.wg_count = grid;
   if (d.free_mask) {
     if (hipMemsetAsync(d.free_mask, 0, (size_t)((d.n + 31) / 32) * 4, s) != hipSuccess) return PGDTO_ERR_HIP;
   }

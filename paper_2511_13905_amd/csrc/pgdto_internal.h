@@ -43,6 +43,8 @@ struct Desc {
   int32_t tile_base[PGDTO_MAX_BLOCKS + 1];
   int64_t tile_elems;
   int32_t ntiles;
+  // workgroups that solve this instance: blockIdx.x in [wg_base, wg_base + wg_count)
+  int32_t wg_base, wg_count;
   // Algorithm 3 step (pgd != 0)
   int32_t pgd, cg_rule, fallback_forced, zero_step;   // zero_step: t == 0
   const void* rho;
@@ -77,9 +79,40 @@ inline int64_t tile_unit(int dtype) { return (int64_t)BLOCK * vec_elems(dtype) *
 
 }  // namespace pgdto
 
-// Launchers (pgdto_kernels.hip)
+// ------------------------------------------------------------------ server
+// Persistent multi-slot executor (continuous batching).  The host publishes
+// job descriptors in pinned host memory; the slots of one long-running launch
+// claim them in order, each slot solving one instance on its own workgroups
+// with its own synchronisation words, and report completion in pinned memory.
 namespace pgdto {
+
+struct SrvHostCtl {            // pinned host memory, written by the host
+  uint64_t tail;               // number of jobs published
+  uint64_t pad0[15];
+  uint64_t shutdown;           // non-zero: slots leave once the queue is empty
+  uint64_t pad1[15];
+};
+
+struct SrvArgs {
+  SrvHostCtl* ctl;             // pinned
+  const Desc* jobs;            // pinned [qcap]: job j at j % qcap
+  uint64_t* done;              // pinned [qcap]: j + 1 once job j finished
+  pgdto_result* results;       // pinned [qcap]
+  uint64_t* head;              // device: next job to claim
+  uint64_t* slot_words;        // device: [slots][16]: broadcast sequence, job index
+  double* part;                // device: per-slot partial sums, stride part_stride
+  uint64_t* sync;              // device: per-slot barrier words, stride sync_stride
+  uint64_t part_stride, sync_stride;
+  uint64_t round0;             // launch-unique base of the broadcast sequence
+  int32_t slots, wg_per_slot, qcap;
+  uint32_t idle_spins;         // master polls without a job before the slot leaves
+};
+
+constexpr uint64_t SRV_LEAVE = ~0ull;
+
 hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative);
 int max_coresident(int kind, int dtype, int m, int device);
 hipError_t launch_mark_error(void* result, int is_pgd, hipStream_t stream);
+hipError_t launch_server(const SrvArgs& a, hipStream_t stream);
+int server_coresident(int device);     // workgroups of the server kernel that fit at once
 }  // namespace pgdto

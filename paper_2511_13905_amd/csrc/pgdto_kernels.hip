@@ -189,13 +189,19 @@ __device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const i
 
 __device__ __forceinline__ uint64_t clk() { return __builtin_amdgcn_s_memrealtime(); }
 
+// This workgroup's index among the workgroups that solve the instance, and
+// their number (a one-instance launch: blockIdx.x and gridDim.x; a server
+// slot: its own range of the grid).
+__device__ __forceinline__ int wg_id(const Desc& d) { return (int)blockIdx.x - d.wg_base; }
+__device__ __forceinline__ int wg_num(const Desc& d) { return d.wg_count; }
+
 __device__ __forceinline__ void trace_put(const Desc& d, int pass, int slot, uint64_t v) {
-  if (d.trace && blockIdx.x == 0 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
+  if (d.trace && wg_id(d) == 0 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
 }
 // per-workgroup records of each pass, after the per-pass records: loop start,
 // loop end, go seen (end of the pass's wait), hardware ids (HW_ID | XCC_ID << 32)
 __device__ __forceinline__ uint64_t* trace_wg_rec(const Desc& d, int pass) {
-  return d.trace + TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + blockIdx.x) * TRACE_WG_W;
+  return d.trace + TRACE_MAX * TRACE_W + ((size_t)pass * GMAX + wg_id(d)) * TRACE_WG_W;
 }
 __device__ __forceinline__ void trace_wg(const Desc& d, int pass, uint64_t t_start, uint64_t t_end) {
   if (d.trace && threadIdx.x == 0 && pass < TRACE_WG_PASSES) {
@@ -213,7 +219,7 @@ __device__ __forceinline__ void trace_wg_go(const Desc& d, int pass, uint64_t t)
 }
 // records of the last workgroup (slots 6, 7)
 __device__ __forceinline__ void trace_last(const Desc& d, int pass, int slot, uint64_t v) {
-  if (d.trace && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
+  if (d.trace && wg_id(d) == wg_num(d) - 1 && threadIdx.x == 0 && pass < TRACE_MAX) d.trace[pass * TRACE_W + slot] = v;
 }
 
 // ------------------------------------------------------------------ grid synchronisation
@@ -250,16 +256,17 @@ __device__ __forceinline__ SyncWords sync_words(const Desc& d) {
 __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const double* pb, int nv, uint64_t maxmask,
                             int nseg, double* tot, int32_t* abort_flag, int pass_no) {
   const SyncWords W = sync_words(d);
-  const int G = gridDim.x;
+  const int G = wg_num(d);
+  const int wid = wg_id(d);
   const int ntot = nseg * nv;
   const bool in_rep = ntot <= REP_VALS;
   __syncthreads();
   if (threadIdx.x == 0) {
     *abort_flag = 0;
-    __hip_atomic_store(&W.flags[(size_t)blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&W.flags[(size_t)wid * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  if (blockIdx.x == 0) {
+  if (wid == 0) {
     bool ok = true;
     for (int w = threadIdx.x; w < G && ok; w += BLOCK) {
       uint32_t spins = 0;
@@ -296,7 +303,7 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
     return true;
   }
   trace_last(d, pass_no, 6, clk());
-  uint64_t* my = W.rep + (size_t)(blockIdx.x % NREP) * REP_WORDS;
+  uint64_t* my = W.rep + (size_t)(wid % NREP) * REP_WORDS;
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
     bool ok = true;
@@ -329,7 +336,7 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
 
 // Workgroup 0 reports a timeout of this launch in the result.
 __device__ void report_error(const Desc& d, int32_t* err_field) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && err_field) {
+  if (wg_id(d) == 0 && threadIdx.x == 0 && err_field) {
     const SyncWords W = sync_words(d);
     if (__hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == d.epoch0)
       *err_field = PGDTO_ERR_TIMEOUT;
@@ -620,14 +627,11 @@ struct Sh1D {
 };
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
+__device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   constexpr int V = VT<T>::N;
-  __shared__ Sh1D sh;
-  __shared__ Desc sd;
-  load_desc(sd);
-  const Desc& d = sd;
   const int tid = threadIdx.x;
-  const int G = gridDim.x;
+  const int G = wg_num(d);
+  const int wid = wg_id(d);
   const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi), kappa = d.kappa;
 
   if (tid == 0) {
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
     trace_put(d, pass_no, 0, ((uint64_t)PH_PGD_R << 56) | (t_pass0 & 0x00ffffffffffffffull));
     const int nv = 8;
     const uint64_t maxmask = 1ull << 6;
-    for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
+    for (int tile = wid; tile < d.ntiles; tile += G) {
       const TileGeom g = tile_geom<T>(d, tile);
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       // s = rho_t - rho_{t-1}, y = grad_t - grad_{t-1}: |s|^2, |y|^2, s.y, |g|^2,
@@ -757,7 +761,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
     int nv = 0;
     uint64_t maxmask = 0;
 
-    for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
+    for (int tile = wid; tile < d.ntiles; tile += G) {
       const TileGeom g = tile_geom<T>(d, tile);
       const int s = g.seg;
       if (ph == PH_ZERO) {
@@ -776,7 +780,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
           acc[4] += fabs(av);
           if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
         };
-        if (tile == (int)blockIdx.x && g.nsweep <= RS) {
+        if (tile == wid && g.nsweep <= RS) {
           // load (pgd: form) this workgroup's first tile into registers
           const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
 #pragma unroll
@@ -899,7 +903,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
               acc[3] += (x1 == z1) ? a2 : 0.0;
             }
           };
-          if (tile == (int)blockIdx.x && resident) {
+          if (tile == wid && resident) {
 #pragma unroll
             for (int k = 0; k < RS; ++k)
 #pragma unroll
@@ -943,7 +947,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
           st_vec<T>(X, e0, mask, full, xo);
           return bits;
         };
-        if (tile == (int)blockIdx.x && resident) {
+        if (tile == wid && resident) {
           // rho_t of slot k + 1 is requested before x of slot k is stored
           // (the store may alias it), so the loads overlap the slot work
           T rnext[V];
@@ -1043,7 +1047,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
         sh.phase = any ? PH_SEARCH : PH_FINAL;
       }
     } else {  // PH_FINAL: results (workgroup 0 writes)
-      if (blockIdx.x == 0) {
+      if (wid == 0) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         for (int s = tid; s < d.nseg; s += BLOCK) {
           R->lambda[s] = sh.S.lam[s];
@@ -1095,6 +1099,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
   int32_t* errp = nullptr;
   if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
   report_error(d, errp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
+  __shared__ Sh1D sh;
+  __shared__ Desc sd;
+  load_desc(sd);
+  solve_1d<T>(sh, sd);
 }
 
 // ================================================================== coupled kernel
@@ -1345,15 +1357,12 @@ __device__ int newton_after_trial(ShC& sh) {
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
+__device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
   constexpr int V = VT<T>::N;
   using C = CN<M>;
-  __shared__ ShC sh;
-  __shared__ Desc sd;
-  load_desc(sd);
-  const Desc& d = sd;
   const int tid = threadIdx.x;
-  const int G = gridDim.x;
+  const int G = wg_num(d);
+  const int wid = wg_id(d);
   const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi), kappa = d.kappa;
 
   if (tid == 0) {
@@ -1405,7 +1414,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
       default: nv = C::NV_FINAL; break;
     }
 
-    for (int tile = blockIdx.x; tile < d.ntiles; tile += G) {
+    for (int tile = wid; tile < d.ntiles; tile += G) {
       const TileGeom g = tile_geom<T>(d, tile);
       if (ph == PH_PGD_R) {
         double acc[C::NV_R];
@@ -1776,7 +1785,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
         }
       }
     } else {  // PH_FINAL
-      if (blockIdx.x == 0) {
+      if (wid == 0) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         if (tid < M) {
           const int j = tid;
@@ -1830,6 +1839,149 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
   report_error(d, errp);
 }
 
+template <typename T, int M>
+__global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
+  __shared__ ShC sh;
+  __shared__ Desc sd;
+  load_desc(sd);
+  solve_coupled<T, M>(sh, sd);
+}
+
+// ================================================================== server kernel
+// Continuous batching: slot s owns workgroups [s * W, (s + 1) * W) of one
+// long-running launch.  Its first workgroup claims the next published job
+// (one compare-and-swap on the device-wide head counter), broadcasts it to
+// the slot, every workgroup of the slot copies the job's descriptor, clears
+// the free-mask words of its tiles and runs the same solver as a one-instance
+// launch on W workgroups, with the slot's own partial sums and barrier words.
+// Results are bitwise those of a one-instance launch: the reduction order
+// follows the tiles, which depend only on n and the dtype.  A slot leaves
+// when the host sets shutdown and no job is left, or after idle_spins polls
+// without a job (the host launches the kernel again when new work comes).
+// float32 streams only.
+
+union ShSrv {
+  Sh1D s1;
+  ShC sc;
+};
+
+template <typename T>
+__device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
+  if (!d.free_mask) return;
+  const int wid = wg_id(d), G = wg_num(d);
+  for (int tile = wid; tile < d.ntiles; tile += G) {
+    const TileGeom g = tile_geom<T>(d, tile);
+    const int64_t w0 = g.ts >> 5, w1 = (g.te + 31) >> 5;
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += BLOCK) d.free_mask[w] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
+  __shared__ SrvArgs a;
+  __shared__ ShSrv sh;
+  __shared__ Desc sd;
+  __shared__ int64_t job;
+  __shared__ int32_t leave;
+  {
+    const uint32_t* src = (const uint32_t*)__builtin_amdgcn_kernarg_segment_ptr();
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
+    for (int i = threadIdx.x; i < (int)(sizeof(SrvArgs) / 4); i += BLOCK) dst[i] = src[i];
+    __syncthreads();
+  }
+  const int W = a.wg_per_slot;
+  const int slot = (int)blockIdx.x / W;
+  const int vb = (int)blockIdx.x - slot * W;
+  uint64_t* sw = a.slot_words + (size_t)slot * 16;
+  for (uint64_t r = 1;; ++r) {
+    const uint64_t seq = a.round0 + r;
+    if (threadIdx.x == 0) {
+      int64_t j = -1;
+      int out = 0;
+      if (vb == 0) {
+        uint32_t spins = 0;
+        for (;;) {
+          const uint64_t tail = __hip_atomic_load(&a.ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          uint64_t h = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (h < tail) {
+            if (__hip_atomic_compare_exchange_strong(a.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+              j = (int64_t)h;
+              break;
+            }
+            continue;
+          }
+          if (__hip_atomic_load(&a.ctl->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0 ||
+              ++spins > a.idle_spins) {
+            out = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(32);
+        }
+        __hip_atomic_store(sw + 1, out ? SRV_LEAVE : (uint64_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(sw, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        // bounded: well beyond the master's idle time
+        uint32_t spins = 0;
+        while (__hip_atomic_load(sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < seq) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++spins > 16u * a.idle_spins + SPIN_LIMIT) { out = 1; break; }
+        }
+        if (!out) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          const uint64_t v = __hip_atomic_load(sw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v == SRV_LEAVE) out = 1; else j = (int64_t)v;
+        }
+      }
+      job = j;
+      leave = out;
+    }
+    __syncthreads();
+    if (leave) return;
+    const int64_t jb = job;
+    const int q = (int)(jb % a.qcap);
+    {
+      // the job descriptor (pinned host memory, published before tail)
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.jobs + q);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&sd);
+      for (int i = threadIdx.x; i < (int)(sizeof(Desc) / 4); i += BLOCK)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        sd.wg_base = slot * W;
+        sd.wg_count = W;
+        sd.part = a.part + (size_t)slot * a.part_stride;
+        sd.sync = a.sync + (size_t)slot * a.sync_stride;
+        sd.result = a.results + q;
+        sd.trace = nullptr;
+        sd.pgd = 0;
+      }
+      __syncthreads();
+    }
+    clear_mask_tiles<float>(sd);
+    if (sd.kind == PGDTO_COUPLED) {
+      switch (sd.m) {
+        case 1: solve_coupled<float, 1>(sh.sc, sd); break;
+        case 2: solve_coupled<float, 2>(sh.sc, sd); break;
+        case 3: solve_coupled<float, 3>(sh.sc, sd); break;
+        case 4: solve_coupled<float, 4>(sh.sc, sd); break;
+        case 5: solve_coupled<float, 5>(sh.sc, sd); break;
+        case 6: solve_coupled<float, 6>(sh.sc, sd); break;
+        case 7: solve_coupled<float, 7>(sh.sc, sd); break;
+        default: solve_coupled<float, 8>(sh.sc, sd); break;
+      }
+    } else {
+      solve_1d<float>(sh.s1, sd);
+    }
+    __syncthreads();
+    if (vb == 0 && threadIdx.x == 0) {
+      // the result (written by this workgroup) before the completion word
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      __hip_atomic_store(a.done + q, (uint64_t)jb + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
 // Marks a result as failed (used by the host after a failed launch).
 __global__ void k_mark_error(void* result, int is_pgd) {
   if (threadIdx.x == 0 && result) {
@@ -1872,6 +2024,19 @@ hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooper
   const void* fn = kernel_fn(d.kind, d.dtype, d.m);
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
   return hipLaunchKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
+}
+
+hipError_t launch_server(const SrvArgs& a, hipStream_t stream) {
+  SrvArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel((const void*)k_server, dim3(a.slots * a.wg_per_slot), dim3(BLOCK), args, 0, stream);
+}
+
+int server_coresident(int device) {
+  int nb = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_server, BLOCK, 0) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return nb * ncu;
 }
 
 hipError_t launch_mark_error(void* result, int is_pgd, hipStream_t stream) {

@@ -4,7 +4,7 @@
 // keeps the summed footprint (y, A, x bytes) of the requests in flight under
 // the configured HBM budget.  This file holds the request bookkeeping and the
 // one-at-a-time executor; the slot-based persistent executor lives in
-// pgdto_server.hip.
+// pgdto_server.cpp.
 
 #include <hip/hip_runtime.h>
 
@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -24,6 +25,11 @@
 #include "pgdto_serve.h"
 
 namespace pgdto {
+
+static int64_t clock_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
 
 size_t request_footprint(const pgdto_problem& p) {
   const size_t esz = p.dtype == PGDTO_F32 ? 4 : 8;
@@ -95,6 +101,21 @@ extern "C" int pgdto_batch_wait(pgdto_batch* b, uint64_t ticket, pgdto_result* o
   return b->poll(ticket, out, true);
 }
 
+extern "C" int pgdto_batch_poll_timed(pgdto_batch* b, uint64_t ticket, pgdto_result* out, int64_t* times,
+                                      int wait) {
+  if (!b || !out || !times) return PGDTO_ERR_ARG;
+  return b->poll(ticket, out, wait != 0, times);
+}
+
+extern "C" int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot) {
+  if (!b || !slots || !wg_per_slot) return PGDTO_ERR_ARG;
+  int s = 0, w = 0;
+  if (b->server && server_shape(b, &s, &w) != PGDTO_OK) return PGDTO_ERR_ARG;
+  *slots = s;
+  *wg_per_slot = w;
+  return PGDTO_OK;
+}
+
 extern "C" int pgdto_batch_stats(pgdto_batch* b, int64_t* admitted, int64_t* completed, int64_t* queued,
                                  int64_t* in_flight, int64_t* peak_bytes) {
   if (!b) return PGDTO_ERR_ARG;
@@ -123,14 +144,14 @@ int pgdto_batch::submit(const Request& r0, uint64_t* ticket) {
   Request r = r0;
   r.ticket = next_ticket++;
   r.state = PGDTO_QUEUED;
-  records[r.ticket] = Record{PGDTO_QUEUED, {}};
+  records[r.ticket] = Record{PGDTO_QUEUED, {}, clock_ns(), 0, 0};
   queue.push_back(r);
   *ticket = r.ticket;
   cv.notify_all();
   return PGDTO_OK;
 }
 
-int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait) {
+int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait, int64_t* times) {
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     auto it = records.find(ticket);
@@ -138,6 +159,11 @@ int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait) {
     const int st = it->second.state;
     if (st == PGDTO_OK || st < 0) {
       *out = it->second.result;
+      if (times) {
+        times[0] = it->second.t_submit;
+        times[1] = it->second.t_start;
+        times[2] = it->second.t_done;
+      }
       records.erase(it);
       return st;
     }
@@ -146,12 +172,15 @@ int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait) {
   }
 }
 
-void pgdto_batch::finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint) {
+void pgdto_batch::finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint, int64_t t_start,
+                         int64_t t_done) {
   std::lock_guard<std::mutex> lk(mu);
   auto it = records.find(ticket);
   if (it != records.end()) {
     it->second.state = status;
     it->second.result = res;
+    it->second.t_start = t_start;
+    it->second.t_done = t_done;
   }
   n_completed += 1;
   n_in_flight -= 1;
@@ -205,21 +234,21 @@ void pgdto_batch::run_plain() {
     p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
     pgdto_result res;
     memset(&res, 0, sizeof(res));
+    const int64_t t0 = clock_ns();
     int st = pgdto_project(plain_ctx, &p, &r.params, &res, (void*)plain_stream);
-    finish(r.ticket, st, res, r.footprint);
+    if (st == PGDTO_OK && res.error != 0) st = res.error;
+    finish(r.ticket, st, res, r.footprint, t0, clock_ns());
   }
 }
 
+// max_slots == 1: the plain one-at-a-time executor; otherwise the persistent
+// multi-slot server.
 int pgdto_batch::start() {
+  if (cfg.max_slots != 1) return server_start(this);
   if (hipStreamCreateWithFlags(&plain_stream, hipStreamNonBlocking) != hipSuccess) return PGDTO_ERR_HIP;
   int st = pgdto_ctx_create(ctx->device, &plain_ctx);
   if (st != PGDTO_OK) return st;
-  if (cfg.max_slots > 1 || cfg.max_slots == 0) {
-    st = server_start(this);
-    if (st != PGDTO_OK) return st;
-  } else {
-    worker = std::thread([this] { run_plain(); });
-  }
+  worker = std::thread([this] { run_plain(); });
   return PGDTO_OK;
 }
 

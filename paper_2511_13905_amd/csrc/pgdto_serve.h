@@ -27,11 +27,12 @@ struct Request {
 struct Record {
   int state;                 // PGDTO_QUEUED / PGDTO_PENDING / PGDTO_OK / error
   pgdto_result result;
+  int64_t t_submit, t_start, t_done;   // host monotonic clock, ns
 };
 
 size_t request_footprint(const pgdto_problem& p);
 
-struct Server;   // slot-based persistent executor (pgdto_server.hip)
+struct Server;   // slot-based persistent executor (pgdto_server.cpp)
 
 }  // namespace pgdto
 
@@ -57,8 +58,9 @@ struct pgdto_batch {
   int start();
   void stop();
   int submit(const pgdto::Request& r, uint64_t* ticket);
-  int poll(uint64_t ticket, pgdto_result* out, bool wait);
-  void finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint);
+  int poll(uint64_t ticket, pgdto_result* out, bool wait, int64_t* times = nullptr);
+  void finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint, int64_t t_start,
+              int64_t t_done);
   bool pop_admissible(pgdto::Request& r, size_t slots_free);
   void cancel_queued();
   void run_plain();
@@ -67,4 +69,5 @@ struct pgdto_batch {
 namespace pgdto {
 int server_start(pgdto_batch* b);
 void server_stop(pgdto_batch* b);
+int server_shape(pgdto_batch* b, int* slots, int* wg);
 }  // namespace pgdto

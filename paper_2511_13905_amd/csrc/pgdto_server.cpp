@@ -1,0 +1,295 @@
+// Host side of the persistent multi-slot executor (continuous batching).
+//
+// One thread per batch object admits queued requests (within the HBM budget)
+// as job descriptors into a pinned ring, publishes them by advancing `tail`,
+// retires finished jobs from the pinned completion words, and keeps the
+// server kernel running while work is outstanding.  Requests that arrive
+// while others are on the device are admitted as soon as the ring and the
+// budget allow; slots of the running launch claim them as they free up, so
+// requests of different sizes and kinds overlap on the device.
+
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <chrono>
+#include <thread>
+#include <vector>
+
+#include "pgdto_ctx.h"
+#include "pgdto_internal.h"
+#include "pgdto_serve.h"
+
+namespace pgdto {
+
+namespace {
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+}  // namespace
+
+struct Server {
+  pgdto_batch* b = nullptr;
+  int slots = 0, wg = 0, qcap = 0;
+  SrvHostCtl* ctl = nullptr;     // pinned
+  Desc* jobs = nullptr;          // pinned [qcap]
+  uint64_t* done = nullptr;      // pinned [qcap]
+  pgdto_result* results = nullptr;   // pinned [qcap]
+  uint64_t* head = nullptr;      // device
+  uint64_t* slot_words = nullptr;    // device
+  double* part = nullptr;        // device
+  uint64_t* sync = nullptr;      // device
+  hipStream_t stream = nullptr;
+  bool running = false;
+  uint64_t launches = 0;
+  uint64_t published = 0;        // jobs written and published
+  uint64_t oldest = 0;           // oldest job not yet retired
+  struct Out {
+    uint64_t ticket;
+    size_t footprint;
+    int64_t t_start;
+    bool retired;
+  };
+  std::vector<Out> out;          // [qcap], indexed by job % qcap
+  std::thread th;
+
+  int init();
+  void release();
+  void loop();
+  bool retire();
+  bool admit();
+  int ensure_running();
+  void fail_stranded();
+};
+
+int Server::init() {
+  if (hipSetDevice(b->ctx->device) != hipSuccess) return PGDTO_ERR_HIP;
+  const int cap = server_coresident(b->ctx->device);
+  if (cap <= 0) return PGDTO_ERR_HIP;
+  slots = b->cfg.max_slots > 0 ? b->cfg.max_slots : 8;
+  wg = b->cfg.wg_per_slot > 0 ? b->cfg.wg_per_slot : cap / slots;
+  if (wg < 1 || slots * wg > cap || wg > GMAX) return PGDTO_ERR_ARG;
+  qcap = 256;
+  out.assign(qcap, Out{0, 0, 0, true});
+  bool ok = true;
+  ok = ok && hipHostMalloc((void**)&ctl, sizeof(SrvHostCtl), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&jobs, sizeof(Desc) * qcap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&done, sizeof(uint64_t) * qcap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&results, sizeof(pgdto_result) * qcap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMalloc(&head, 256) == hipSuccess;
+  ok = ok && hipMalloc(&slot_words, sizeof(uint64_t) * 16 * slots) == hipSuccess;
+  ok = ok && hipMalloc(&part, sizeof(double) * PART_DOUBLES * slots) == hipSuccess;
+  ok = ok && hipMalloc(&sync, sizeof(uint64_t) * SYNC_WORDS * slots) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) return PGDTO_ERR_NOMEM;
+  memset(ctl, 0, sizeof(SrvHostCtl));
+  memset(jobs, 0, sizeof(Desc) * qcap);
+  memset(done, 0, sizeof(uint64_t) * qcap);
+  memset(results, 0, sizeof(pgdto_result) * qcap);
+  ok = ok && hipMemset(head, 0, 256) == hipSuccess;
+  ok = ok && hipMemset(slot_words, 0, sizeof(uint64_t) * 16 * slots) == hipSuccess;
+  ok = ok && hipMemset(sync, 0, sizeof(uint64_t) * SYNC_WORDS * slots) == hipSuccess;
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
+  return ok ? PGDTO_OK : PGDTO_ERR_HIP;
+}
+
+void Server::release() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (ctl) (void)hipHostFree(ctl);
+  if (jobs) (void)hipHostFree(jobs);
+  if (done) (void)hipHostFree(done);
+  if (results) (void)hipHostFree(results);
+  if (head) (void)hipFree(head);
+  if (slot_words) (void)hipFree(slot_words);
+  if (part) (void)hipFree(part);
+  if (sync) (void)hipFree(sync);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+// Retire finished jobs (completion word = job + 1).
+bool Server::retire() {
+  bool any = false;
+  for (uint64_t j = oldest; j < published; ++j) {
+    Out& o = out[j % qcap];
+    if (o.retired) continue;
+    const uint64_t w = __atomic_load_n(&done[j % qcap], __ATOMIC_ACQUIRE);
+    if (w != j + 1) continue;
+    const pgdto_result& r = results[j % qcap];
+    const int st = r.error != 0 ? r.error : PGDTO_OK;
+    b->finish(o.ticket, st, r, o.footprint, o.t_start, now_ns());
+    o.retired = true;
+    any = true;
+  }
+  while (oldest < published && out[oldest % qcap].retired) ++oldest;
+  return any;
+}
+
+// Admit queued requests into free ring entries, then publish them.
+bool Server::admit() {
+  bool any = false;
+  while (published - oldest < (uint64_t)qcap) {
+    Request r;
+    {
+      std::lock_guard<std::mutex> lk(b->mu);
+      if (!b->pop_admissible(r, 1)) break;
+    }
+    pgdto_problem p = r.prob;
+    p.b = r.b;
+    p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
+    Desc d;
+    int st = build_desc(&p, &r.params, true, d);
+    if (st == PGDTO_OK && p.dtype != PGDTO_F32) st = PGDTO_ERR_ARG;
+    if (st != PGDTO_OK) {
+      pgdto_result res;
+      memset(&res, 0, sizeof(res));
+      b->finish(r.ticket, st, res, r.footprint, now_ns(), now_ns());
+      continue;
+    }
+    const uint64_t j = published;
+    d.epoch0 = (j + 1) << 20;      // per slot barrier words: epochs grow with the job index
+    d.pgd = 0;
+    d.result = nullptr;
+    d.trace = nullptr;
+    jobs[j % qcap] = d;
+    __atomic_store_n(&done[j % qcap], 0, __ATOMIC_RELAXED);
+    out[j % qcap] = Out{r.ticket, r.footprint, now_ns(), false};
+    published = j + 1;
+    any = true;
+  }
+  if (any) __atomic_store_n(&ctl->tail, published, __ATOMIC_RELEASE);
+  return any;
+}
+
+// After the kernel ended: jobs it claimed but did not finish (a device wait
+// timed out) are failed, so that no ticket waits forever.
+void Server::fail_stranded() {
+  uint64_t h = 0;
+  if (hipMemcpy(&h, head, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return;
+  for (uint64_t j = oldest; j < published && j < h; ++j) {
+    Out& o = out[j % qcap];
+    if (o.retired) continue;
+    if (__atomic_load_n(&done[j % qcap], __ATOMIC_ACQUIRE) == j + 1) continue;
+    pgdto_result res;
+    memset(&res, 0, sizeof(res));
+    res.error = PGDTO_ERR_TIMEOUT;
+    b->finish(o.ticket, PGDTO_ERR_TIMEOUT, res, o.footprint, o.t_start, now_ns());
+    o.retired = true;
+  }
+  while (oldest < published && out[oldest % qcap].retired) ++oldest;
+}
+
+int Server::ensure_running() {
+  if (running) {
+    const hipError_t q = hipStreamQuery(stream);
+    if (q == hipErrorNotReady) return PGDTO_OK;
+    running = false;
+    if (q != hipSuccess) return PGDTO_ERR_HIP;
+    retire();
+    fail_stranded();
+  }
+  if (oldest >= published) return PGDTO_OK;      // nothing outstanding
+  SrvArgs a;
+  memset(&a, 0, sizeof(a));
+  a.ctl = ctl;
+  a.jobs = jobs;
+  a.done = done;
+  a.results = results;
+  a.head = head;
+  a.slot_words = slot_words;
+  a.part = part;
+  a.sync = sync;
+  a.part_stride = PART_DOUBLES;
+  a.sync_stride = SYNC_WORDS;
+  a.round0 = (++launches) << 32;
+  a.slots = slots;
+  a.wg_per_slot = wg;
+  a.qcap = qcap;
+  a.idle_spins = 1000;           // a few ms without a job
+  if (launch_server(a, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return PGDTO_ERR_HIP;
+  }
+  running = true;
+  return PGDTO_OK;
+}
+
+void Server::loop() {
+  (void)hipSetDevice(b->ctx->device);
+  int idle_rounds = 0;
+  for (;;) {
+    bool progress = retire();
+    progress |= admit();
+    bool stop = false;
+    {
+      std::lock_guard<std::mutex> lk(b->mu);
+      stop = b->stopping && b->queue.empty();
+    }
+    if (stop && oldest >= published) break;
+    if (ensure_running() != PGDTO_OK) {
+      // the launch failed: fail what is outstanding and what is queued
+      for (uint64_t j = oldest; j < published; ++j) {
+        Out& o = out[j % qcap];
+        if (o.retired) continue;
+        pgdto_result res;
+        memset(&res, 0, sizeof(res));
+        res.error = PGDTO_ERR_HIP;
+        b->finish(o.ticket, PGDTO_ERR_HIP, res, o.footprint, o.t_start, now_ns());
+        o.retired = true;
+      }
+      oldest = published;
+      b->cancel_queued();
+    }
+    if (progress) {
+      idle_rounds = 0;
+      continue;
+    }
+    // nothing changed: spin briefly, then sleep in short steps
+    if (++idle_rounds < 64) {
+      std::this_thread::yield();
+    } else {
+      std::unique_lock<std::mutex> lk(b->mu);
+      b->cv.wait_for(lk, std::chrono::microseconds(oldest < published ? 20 : 2000));
+    }
+  }
+  __atomic_store_n(&ctl->shutdown, 1, __ATOMIC_RELEASE);
+  if (running) (void)hipStreamSynchronize(stream);
+  running = false;
+}
+
+int server_start(pgdto_batch* b) {
+  Server* s = new (std::nothrow) Server();
+  if (!s) return PGDTO_ERR_NOMEM;
+  s->b = b;
+  const int st = s->init();
+  if (st != PGDTO_OK) {
+    s->release();
+    delete s;
+    return st;
+  }
+  b->server = s;
+  s->th = std::thread([s] { s->loop(); });
+  return PGDTO_OK;
+}
+
+void server_stop(pgdto_batch* b) {
+  Server* s = b->server;
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->cv.notify_all();
+  }
+  if (s->th.joinable()) s->th.join();
+  s->release();
+  delete s;
+  b->server = nullptr;
+}
+
+int server_shape(pgdto_batch* b, int* slots, int* wg) {
+  if (!b->server) return PGDTO_ERR_ARG;
+  *slots = b->server->slots;
+  *wg = b->server->wg;
+  return PGDTO_OK;
+}
+
+}  // namespace pgdto

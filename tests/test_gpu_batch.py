@@ -1,0 +1,227 @@
+"""Serving (pgdto_batch) on the GPU: the persistent multi-slot executor and the
+plain path against single-launch projections and the CPU oracle.
+
+Bitwise agreement with pgdto_project follows from the tile-ordered
+reductions (the result does not depend on how many workgroups solve an
+instance).  Every case prints its name before touching the GPU.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_13905_amd import inputs as I
+
+from parity import check, free_from_mask
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2511_13905_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def mixed_requests(seed, count, n_lo=4096, n_hi=120000):
+    """Small requests of the served mix (sizes the oracle checks quickly)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        kind = I.SERVE_KINDS[i % 3]
+        out.append(I.serve_request(int(rng.integers(0, 2**31 - 1)), n, kind))
+    return out
+
+
+def stage(reqs, mask=True):
+    """Device inputs of every request, written before any submit: the
+    executor starts on a request as soon as it is published, in no stream
+    order.  The free mask is deliberately not cleared (the executor does it)."""
+    from paper_2511_13905_amd.api import aligned_rows
+    out = []
+    for p in reqs:
+        fm = torch.full(((p.n + 31) // 32,), -1, dtype=torch.int32, device="cuda:0") if mask else None
+        A = dev(p.A)
+        if p.kind != "independent":
+            A = aligned_rows(A)
+        out.append((dev(p.y), A, fm))
+    torch.cuda.synchronize()
+    return out
+
+
+def submit(B, p, staged):
+    y, A, fm = staged
+    t = B.submit(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=fm)
+    return t, fm
+
+
+def collect(B, t, fm, n):
+    x = B.x_of(t)
+    st, r, times = B.wait(t)
+    torch.cuda.synchronize()
+    mask = free_from_mask(fm.cpu().numpy().view(np.uint32), n) if fm is not None else None
+    return st, r, x.cpu().numpy(), mask, times
+
+
+def single(ctx, p):
+    y, A = dev(p.y), dev(p.A)
+    fm = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+    x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=fm)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), r, free_from_mask(fm.cpu().numpy().view(np.uint32), p.n)
+
+
+def test_server_shape(ctx):
+    from paper_2511_13905_amd.api import Batch
+    say("server shape")
+    B = Batch(ctx, max_slots=4)
+    s, w = B.shape()
+    B.close()
+    assert s == 4 and w >= 1
+    B = Batch(ctx, max_slots=1)
+    assert B.shape() == (0, 0)
+    B.close()
+
+
+@pytest.mark.parametrize("slots", [2, 8])
+def test_server_matches_single_launch_bitwise(ctx, slots):
+    from paper_2511_13905_amd.api import Batch
+    reqs = [I.compliance_3d(3, n=65537), I.multi_material(2, fields=4, n_per=30001),
+            I.volume_com(0, grid=(96, 48)), I.volume_com(1, grid=(64, 32))]
+    say("server vs single launch", slots, [p.n for p in reqs])
+    st_in = stage(reqs)
+    B = Batch(ctx, max_slots=slots)
+    handles = [submit(B, p, s) for p, s in zip(reqs, st_in)]
+    outs = [collect(B, t, fm, p.n) for (t, fm), p in zip(handles, reqs)]
+    B.close()
+    for p, (st, r, x, mask, _) in zip(reqs, outs):
+        assert st == 0, (p.kind, st)
+        xs, rs, ms = single(ctx, p)
+        assert np.array_equal(x, xs), p.kind
+        assert np.array_equal(mask, ms), p.kind
+        assert r["lam"] == rs["lam"] and r["passes"] == rs["passes"], (r, rs)
+
+
+def test_server_alone_and_in_mix(ctx):
+    """The same request gives the same bits alone and inside a busy mix."""
+    from paper_2511_13905_amd.api import Batch
+    probe = I.volume_com(4, grid=(128, 64))
+    say("alone vs mix", probe.n)
+    mix = mixed_requests(7, 30)
+    st_probe = stage([probe, probe])
+    st_mix = stage(mix)
+    B = Batch(ctx, max_slots=8)
+    t, fm = submit(B, probe, st_probe[0])
+    st, r_alone, x_alone, m_alone, _ = collect(B, t, fm, probe.n)
+    assert st == 0
+    handles = [submit(B, p, s) for p, s in zip(mix[:15], st_mix[:15])]
+    tp, fp = submit(B, probe, st_probe[1])
+    handles += [submit(B, p, s) for p, s in zip(mix[15:], st_mix[15:])]
+    st, r_mix, x_mix, m_mix, _ = collect(B, tp, fp, probe.n)
+    outs = [collect(B, t, fm, p.n) for (t, fm), p in zip(handles, mix)]
+    stats = B.stats()
+    B.close()
+    assert st == 0
+    assert np.array_equal(x_alone, x_mix)
+    assert np.array_equal(m_alone, m_mix)
+    assert r_alone["lam"] == r_mix["lam"]
+    ref = oracle.project(probe.kind, probe.y, probe.A, probe.b, probe.lo, probe.hi, probe.C, probe.offsets)
+    check(probe, x_mix, r_mix, ref, free_gpu=m_mix)
+    assert all(o[0] == 0 for o in outs)
+    assert stats["completed"] == 32
+
+
+def test_server_mix_parity(ctx):
+    """A mixed stream of 36 requests, every result against the oracle."""
+    from paper_2511_13905_amd.api import Batch
+    reqs = mixed_requests(11, 36)
+    say("mix parity", len(reqs), sum(p.n for p in reqs))
+    st_in = stage(reqs)
+    B = Batch(ctx, max_slots=8)
+    handles = [submit(B, p, s) for p, s in zip(reqs, st_in)]
+    outs = [collect(B, t, fm, p.n) for (t, fm), p in zip(handles, reqs)]
+    B.close()
+    for p, (st, r, x, mask, times) in zip(reqs, outs):
+        assert st == 0, (p.kind, p.n, st)
+        assert times[0] <= times[1] <= times[2]
+        ref = oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets)
+        check(p, x, r, ref, free_gpu=mask)
+
+
+def test_plain_path_matches(ctx):
+    from paper_2511_13905_amd.api import Batch
+    reqs = mixed_requests(5, 6)
+    say("plain path", [p.n for p in reqs])
+    st_in = stage(reqs)
+    B = Batch(ctx, max_slots=1)
+    handles = [submit(B, p, s) for p, s in zip(reqs, st_in)]
+    outs = [collect(B, t, fm, p.n) for (t, fm), p in zip(handles, reqs)]
+    B.close()
+    for p, (st, r, x, mask, _) in zip(reqs, outs):
+        assert st == 0
+        xs, rs, ms = single(ctx, p)
+        assert np.array_equal(x, xs)
+        assert np.array_equal(mask, ms)
+
+
+def test_server_idle_exit_and_relaunch(ctx):
+    """The launch ends after ~50 ms without work; a later request starts it again."""
+    from paper_2511_13905_amd.api import Batch
+    say("idle relaunch")
+    p1 = I.compliance_3d(1, n=20000)
+    p2 = I.multi_material(3, fields=4, n_per=5000)
+    st_in = stage([p1, p2])
+    B = Batch(ctx, max_slots=4)
+    t, fm = submit(B, p1, st_in[0])
+    assert collect(B, t, fm, p1.n)[0] == 0
+    time.sleep(0.3)
+    t, fm = submit(B, p2, st_in[1])
+    st, r, x, mask, _ = collect(B, t, fm, p2.n)
+    B.close()
+    assert st == 0
+    ref = oracle.project(p2.kind, p2.y, p2.A, p2.b, p2.lo, p2.hi, p2.C, p2.offsets)
+    check(p2, x, r, ref, free_gpu=mask)
+
+
+def test_server_budget_backpressure(ctx):
+    """A tight HBM budget limits the footprint in flight; all requests finish."""
+    from paper_2511_13905_amd.api import Batch
+    reqs = [I.compliance_3d(s, n=200000) for s in range(6)]
+    fp = 4 * 200000 * 3
+    say("budget", fp)
+    st_in = stage(reqs, mask=False)
+    B = Batch(ctx, max_slots=8, hbm_budget_bytes=2 * fp)
+    handles = [submit(B, p, s) for p, s in zip(reqs, st_in)]
+    outs = [collect(B, t, fm, p.n) for (t, fm), p in zip(handles, reqs)]
+    stats = B.stats()
+    B.close()
+    assert all(o[0] == 0 for o in outs)
+    assert stats["peak_bytes"] <= 2 * fp
+
+
+def test_server_rejects_f64(ctx):
+    from paper_2511_13905_amd.api import Batch
+    from paper_2511_13905_amd import _native as N
+    p = I.volume_2d(0)
+    say("server f64 request")
+    st_in = stage([p])
+    B = Batch(ctx, max_slots=2)
+    t, fm = submit(B, p, st_in[0])
+    st, r, _ = B.wait(t)
+    B.close()
+    assert st == N.ERR_ARG
