@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--instances", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream and batched measurements")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-pool", type=int, default=128,
+                    help="distinct request instances the served stream cycles through")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -211,10 +215,155 @@ def main():
         "roofline_compulsory": {"bytes": compulsory, "achieved": compulsory / (kern_ms * 1e-3) / 1e9,
                                 "unit": "GB/s", "frac": compulsory / (kern_ms * 1e-3) / HBM_PEAK},
     }
+    if not args.no_serve:
+        line["serving"] = serve_bench(ctx, args)
+        line["batched"] = batched_bench(ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, insts, args.cpu_seconds, n)
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def _pctl(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
+
+def _run_stream(ctx, structs, params, max_slots, arrivals):
+    """Submit the pre-built requests at the given arrival offsets (s) through
+    one pgdto_batch; returns per-request (submit, admit, done) ns and statuses."""
+    import ctypes as C
+    from paper_2511_13905_amd import _native as N
+    from paper_2511_13905_amd.api import Batch
+    L = N.lib()
+    B = Batch(ctx, max_slots=max_slots)
+    tickets = []
+    t0 = time.perf_counter()
+    for st, at in zip(structs, arrivals):
+        while time.perf_counter() - t0 < at:
+            pass
+        t = C.c_uint64()
+        rc = L.pgdto_batch_submit(B.h, C.byref(st), C.byref(params), C.byref(t))
+        if rc != 0:
+            raise RuntimeError(f"submit failed: {rc}")
+        tickets.append(t.value)
+    times, status = [], []
+    r = N.Result()
+    tm = (C.c_int64 * 3)()
+    for t in tickets:
+        rc = L.pgdto_batch_poll_timed(B.h, t, C.byref(r), tm, 1)
+        status.append(rc)
+        times.append((tm[0], tm[1], tm[2]))
+    shape = B.shape()
+    B.close()
+    return times, status, shape
+
+
+def _stream_stats(times, status, ns):
+    lat = [(d - s) / 1e6 for s, a, d in times]
+    svc = [(d - a) / 1e6 for s, a, d in times]
+    wall = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
+    return {"requests": len(times), "errors": sum(1 for x in status if x != 0), "wall_s": wall,
+            "requests_per_s": len(times) / wall, "elements_per_s": sum(ns) / wall,
+            "latency_ms": {"p50": _pctl(lat, 0.5), "p99": _pctl(lat, 0.99), "max": max(lat)},
+            "service_ms": {"p50": _pctl(svc, 0.5), "p99": _pctl(svc, 0.99)}}
+
+
+def serve_bench(ctx, args):
+    """Served stream: requests of n log-uniform in [4096, 2097152], kind uniform
+    over 1 row / 4 independent blocks / 5 coupled rows, float32.  The first
+    `pool` requests of the stream are generated; request i uses instance
+    i mod pool (inputs shared, outputs distinct).  Measures the plain
+    one-at-a-time path and the persistent multi-slot executor, saturated (all
+    requests at t = 0) and with Poisson arrivals at 0.7x and 2x the plain
+    path's saturated rate."""
+    import numpy as np
+    import torch
+    from paper_2511_13905_amd import inputs as I
+    from paper_2511_13905_amd.api import make_params, problem_struct, aligned_rows, _Keep
+    stream = I.serve_stream(0, args.serve_requests)
+    P = min(args.serve_pool, len(stream))
+    pool = [I.serve_request(s, n, kind) for (s, kind, n) in stream[:P]]
+    dev = []
+    for p in pool:
+        A = torch.from_numpy(np.ascontiguousarray(p.A)).to("cuda:0")
+        if p.kind != "independent":
+            A = aligned_rows(A)
+        dev.append((torch.from_numpy(np.ascontiguousarray(p.y)).to("cuda:0"), A))
+    keep = _Keep()
+    structs, ns, xs = [], [], []
+    for i in range(len(stream)):
+        p = pool[i % P]
+        y, A = dev[i % P]
+        x = torch.empty(p.n, dtype=torch.float32, device="cuda:0")
+        st, _, _ = problem_struct(p.kind, y, A, p.b, p.lo, p.hi, p.C, p.offsets, x, None, keep, copy_ok=False)
+        structs.append(st)
+        ns.append(p.n)
+        xs.append(x)
+    torch.cuda.synchronize()
+    params = make_params()
+    rng = np.random.default_rng(1)
+    out = {"workload": f"{len(stream)} requests, n log-uniform [4096, 2097152] (mean {np.mean(ns):.0f}), "
+                       f"kinds 1 row / 4 independent / 5 coupled, float32, {P} distinct instances",
+           "bytes_in_requests": int(sum(4 * p.n * ((1 if p.kind == 'independent' else p.m) + 2) for p in pool))}
+    zero = [0.0] * len(stream)
+    t, s, _ = _run_stream(ctx, structs, params, 1, zero)
+    out["plain_saturated"] = _stream_stats(t, s, ns)
+    t, s, shape = _run_stream(ctx, structs, params, 0, zero)
+    out["server_saturated"] = _stream_stats(t, s, ns)
+    out["server_shape"] = {"slots": shape[0], "wg_per_slot": shape[1]}
+    r_plain = out["plain_saturated"]["requests_per_s"]
+    for name, f in (("0.7x", 0.7), ("2x", 2.0)):
+        rate = f * r_plain
+        arr = np.cumsum(rng.exponential(1.0 / rate, len(stream))).tolist()
+        res = {"rate_per_s": rate}
+        t, s, _ = _run_stream(ctx, structs, params, 1, arr)
+        res["plain"] = _stream_stats(t, s, ns)
+        t, s, _ = _run_stream(ctx, structs, params, 0, arr)
+        res["server"] = _stream_stats(t, s, ns)
+        out[f"poisson_{name}_plain_rate"] = res
+    del xs
+    return out
+
+
+def batched_bench(ctx):
+    """32 projections of the 256x128x128 single-row problem (8 distinct
+    instances, distinct outputs) through the persistent executor, all
+    submitted at once: algorithmic bytes of every pass over wall time."""
+    import numpy as np
+    import torch
+    from paper_2511_13905_amd import inputs as I
+    from paper_2511_13905_amd.api import make_params, problem_struct, _Keep
+    pool = [I.compliance_3d(s) for s in range(8)]
+    dev = [(torch.from_numpy(p.y).to("cuda:0"), torch.from_numpy(p.A).to("cuda:0")) for p in pool]
+    keep = _Keep()
+    structs, xs = [], []
+    for i in range(32):
+        p = pool[i % 8]
+        y, A = dev[i % 8]
+        x = torch.empty(p.n, dtype=torch.float32, device="cuda:0")
+        st, _, _ = problem_struct(p.kind, y, A, p.b, p.lo, p.hi, p.C, None, x, None, keep, copy_ok=False)
+        structs.append(st)
+        xs.append(x)
+    torch.cuda.synchronize()
+    params = make_params()
+    _run_stream(ctx, structs[:8], params, 0, [0.0] * 8)      # warm-up
+    times, status, shape = _run_stream(ctx, structs, params, 0, [0.0] * 32)
+    wall = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
+    n = pool[0].n
+    # passes: from one single-launch run per instance (same bits and pass count)
+    from paper_2511_13905_amd.api import Context
+    passes = []
+    for p, (y, A) in zip(pool, dev):
+        _, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C)
+        passes.append(r["passes"])
+    per = [passes[i % 8] for i in range(32)]
+    alg = sum(pp * n * 8 + n * 4 for pp in per)
+    return {"workload": "32 x project, single compliance row, 256x128x128 (n=4194304), float32, 8 distinct inputs",
+            "errors": sum(1 for x in status if x != 0), "wall_s": wall, "projections_per_s": 32 / wall,
+            "elements_per_s": 32 * n / wall, "passes_mean": sum(per) / 32,
+            "algorithmic_GBps": alg / wall / 1e9, "hbm_frac": alg / wall / HBM_PEAK,
+            "server_shape": {"slots": shape[0], "wg_per_slot": shape[1]}}
 
 
 def cpu_baseline(wl, insts, budget_s, n):

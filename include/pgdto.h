@@ -232,6 +232,10 @@ typedef struct {
   int32_t max_slots;         /* 1: plain path; 0: 8 slots; else slot count   */
   int32_t wg_per_slot;       /* workgroups per slot (0: all that fit / slots) */
   int32_t queue_capacity;    /* pending requests (0: 65536)                   */
+  int32_t slots_only;        /* persistent executor: non-zero sends a lone
+                                request to a slot too (default: a lone request
+                                with nothing else on the device runs as one
+                                full-GPU launch; same bits either way)        */
 } pgdto_batch_cfg;
 
 int pgdto_batch_create(pgdto_ctx* ctx, const pgdto_batch_cfg* cfg, pgdto_batch** out);

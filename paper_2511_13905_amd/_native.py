@@ -85,7 +85,7 @@ class PgdOut(C.Structure):
 
 class BatchCfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
-                ("wg_per_slot", C.c_int32), ("queue_capacity", C.c_int32)]
+                ("wg_per_slot", C.c_int32), ("queue_capacity", C.c_int32), ("slots_only", C.c_int32)]
 
 
 STRUCTS = [Problem, Params, Result, PgdArgs, PgdOut, BatchCfg]

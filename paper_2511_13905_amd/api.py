@@ -241,12 +241,13 @@ class Batch:
     it never copies A: rows must already be 16-byte aligned (aligned_rows)."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 0, wg_per_slot: int = 0,
-                 queue_capacity: int = 0):
+                 queue_capacity: int = 0, slots_only: bool = False):
         cfg = N.BatchCfg()
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.max_slots = int(max_slots)
         cfg.wg_per_slot = int(wg_per_slot)
         cfg.queue_capacity = int(queue_capacity)
+        cfg.slots_only = 1 if slots_only else 0
         h = C.c_void_p()
         _check(N.lib().pgdto_batch_create(ctx.h, C.byref(cfg), C.byref(h)), "pgdto_batch_create")
         self.h = h

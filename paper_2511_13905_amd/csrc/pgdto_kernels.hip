@@ -626,9 +626,11 @@ struct Sh1D {
   int32_t phase, abort_flag, passes, pad;
 };
 
-template <typename T>
+// SU: vector slots in flight per stream in the streaming passes.
+template <typename T, int SU = 2>
 __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   constexpr int V = VT<T>::N;
+  constexpr int SU1 = SU > 2 ? SU / 2 : 1;     // for the 3- to 5-stream passes
   const int tid = threadIdx.x;
   const int G = wg_num(d);
   const int wid = wg_id(d);
@@ -668,7 +670,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       // g.(g - g_prev), |g_prev|^2, |g|_inf, a.rho_t
       if (d.zero_step) {
         const T* ptr[3] = {(const T*)d.rho, (const T*)d.grad, A};
-        stream_tile<T, 3, 1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+        stream_tile<T, 3, SU1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
@@ -680,7 +682,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         });
       } else {
         const T* ptr[5] = {(const T*)d.rho, (const T*)d.grad, A, (const T*)d.rho_prev, (const T*)d.grad_prev};
-        stream_tile<T, 5, 1>(g, d.n, ptr, [&](const T (&b)[5][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+        stream_tile<T, 5, SU1>(g, d.n, ptr, [&](const T (&b)[5][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
@@ -863,18 +865,18 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           };
           if (d.zero_step) {
             const T* ptr[3] = {A, (const T*)d.rho, (const T*)d.grad};
-            stream_tile<T, 3, 1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+            stream_tile<T, 3, SU1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
               body(b[0], b[1], b[2], nullptr, e0, mask, full);
             });
           } else {
             const T* ptr[4] = {A, (const T*)d.rho, (const T*)d.grad, (const T*)d.dir};
-            stream_tile<T, 4, 1>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+            stream_tile<T, 4, SU1>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
               body(b[0], b[1], b[2], b[3], e0, mask, full);
             });
           }
         } else {
           const T* ptr[2] = {Y, A};
-          stream_tile<T, 2, 2>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+          stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
             for (int q = 0; q < V; ++q)
               if (mask & (1u << q)) zero_elem(f64(b[0][q]), f64(b[1][q]));
@@ -910,7 +912,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               for (int q = 0; q < V; ++q) elem(f64(ry[k][q]), f64(ra[k][q]));
           } else {
             const T* ptr[2] = {Y, A};
-            stream_tile<T, 2, 2>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+            stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
               for (int q = 0; q < V; ++q) {
                 const bool ok = (mask >> q) & 1u;

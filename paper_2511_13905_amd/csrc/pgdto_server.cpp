@@ -7,6 +7,11 @@
 // while others are on the device are admitted as soon as the ring and the
 // budget allow; slots of the running launch claim them as they free up, so
 // requests of different sizes and kinds overlap on the device.
+//
+// At light load (one request waiting, nothing on the device) the request
+// runs instead as one full-GPU launch: a slot holds only 1/slots of the GPU,
+// so a lone request finishes sooner on all of it.  Both routes give the same
+// bits (reductions follow the tiles, not the workgroups).
 
 #include <hip/hip_runtime.h>
 
@@ -42,6 +47,16 @@ struct Server {
   uint64_t* sync = nullptr;      // device
   hipStream_t stream = nullptr;
   bool running = false;
+  // full-GPU route for a lone request
+  pgdto_ctx* os_ctx = nullptr;
+  hipStream_t os_stream = nullptr;
+  hipEvent_t os_event = nullptr;
+  pgdto_result* os_res = nullptr;    // pinned
+  bool os_busy = false;
+  uint64_t os_ticket = 0;
+  size_t os_footprint = 0;
+  int64_t os_t_start = 0;
+  int64_t n_oneshot = 0;
   uint64_t launches = 0;
   uint64_t published = 0;        // jobs written and published
   uint64_t oldest = 0;           // oldest job not yet retired
@@ -59,6 +74,7 @@ struct Server {
   void loop();
   bool retire();
   bool admit();
+  bool oneshot();
   int ensure_running();
   void fail_stranded();
 };
@@ -82,6 +98,10 @@ int Server::init() {
   ok = ok && hipMalloc(&part, sizeof(double) * PART_DOUBLES * slots) == hipSuccess;
   ok = ok && hipMalloc(&sync, sizeof(uint64_t) * SYNC_WORDS * slots) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&os_stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&os_event, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&os_res, sizeof(pgdto_result), hipHostMallocDefault) == hipSuccess;
+  ok = ok && pgdto_ctx_create(b->ctx->device, &os_ctx) == PGDTO_OK;
   if (!ok) return PGDTO_ERR_NOMEM;
   memset(ctl, 0, sizeof(SrvHostCtl));
   memset(jobs, 0, sizeof(Desc) * qcap);
@@ -105,6 +125,65 @@ void Server::release() {
   if (part) (void)hipFree(part);
   if (sync) (void)hipFree(sync);
   if (stream) (void)hipStreamDestroy(stream);
+  if (os_stream) (void)hipStreamSynchronize(os_stream);
+  if (os_ctx) pgdto_ctx_destroy(os_ctx);
+  if (os_res) (void)hipHostFree(os_res);
+  if (os_event) (void)hipEventDestroy(os_event);
+  if (os_stream) (void)hipStreamDestroy(os_stream);
+}
+
+// The full-GPU route: retire a finished lone launch; start one when exactly
+// one request waits and nothing else is on the device.
+bool Server::oneshot() {
+  if (os_busy) {
+    const hipError_t q = hipEventQuery(os_event);
+    if (q == hipErrorNotReady) return false;
+    os_busy = false;
+    pgdto_result r = *os_res;
+    int st = q == hipSuccess ? (r.error != 0 ? r.error : PGDTO_OK) : PGDTO_ERR_HIP;
+    if (q != hipSuccess) {
+      (void)hipGetLastError();
+      memset(&r, 0, sizeof(r));
+      r.error = PGDTO_ERR_HIP;
+    }
+    b->finish(os_ticket, st, r, os_footprint, os_t_start, now_ns());
+    return true;
+  }
+  if (b->cfg.slots_only || oldest < published) return false;
+  Request r;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (b->queue.size() != 1 || !b->pop_admissible(r, 1)) return false;
+  }
+  // an idle persistent launch still holds the GPU: ask it to leave now (its
+  // slots exit at their next poll of an empty queue); the full-GPU launch
+  // starts right after it in device order
+  if (running) __atomic_store_n(&ctl->shutdown, 1, __ATOMIC_RELEASE);
+  pgdto_problem p = r.prob;
+  p.b = r.b;
+  p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
+  if (p.dtype != PGDTO_F32) {       // the persistent executor takes float32 only, on either route
+    pgdto_result res;
+    memset(&res, 0, sizeof(res));
+    b->finish(r.ticket, PGDTO_ERR_ARG, res, r.footprint, now_ns(), now_ns());
+    return true;
+  }
+  os_ticket = r.ticket;
+  os_footprint = r.footprint;
+  os_t_start = now_ns();
+  memset(os_res, 0, sizeof(pgdto_result));
+  int st = pgdto_project_async(os_ctx, &p, &r.params, os_res, (void*)os_stream);
+  if (st == PGDTO_OK && hipEventRecord(os_event, os_stream) != hipSuccess) st = PGDTO_ERR_HIP;
+  if (st != PGDTO_OK) {
+    pgdto_result res;
+    memset(&res, 0, sizeof(res));
+    res.error = st;
+    b->finish(r.ticket, st, res, r.footprint, os_t_start, now_ns());
+    return true;
+  }
+  os_busy = true;
+  n_oneshot += 1;
+  return true;
 }
 
 // Retire finished jobs (completion word = job + 1).
@@ -189,6 +268,7 @@ int Server::ensure_running() {
     fail_stranded();
   }
   if (oldest >= published) return PGDTO_OK;      // nothing outstanding
+  __atomic_store_n(&ctl->shutdown, 0, __ATOMIC_RELEASE);   // no launch is running here
   SrvArgs a;
   memset(&a, 0, sizeof(a));
   a.ctl = ctl;
@@ -219,13 +299,14 @@ void Server::loop() {
   int idle_rounds = 0;
   for (;;) {
     bool progress = retire();
+    progress |= oneshot();
     progress |= admit();
     bool stop = false;
     {
       std::lock_guard<std::mutex> lk(b->mu);
       stop = b->stopping && b->queue.empty();
     }
-    if (stop && oldest >= published) break;
+    if (stop && oldest >= published && !os_busy) break;
     if (ensure_running() != PGDTO_OK) {
       // the launch failed: fail what is outstanding and what is queued
       for (uint64_t j = oldest; j < published; ++j) {
@@ -249,7 +330,7 @@ void Server::loop() {
       std::this_thread::yield();
     } else {
       std::unique_lock<std::mutex> lk(b->mu);
-      b->cv.wait_for(lk, std::chrono::microseconds(oldest < published ? 20 : 2000));
+      b->cv.wait_for(lk, std::chrono::microseconds(oldest < published || os_busy ? 20 : 2000));
     }
   }
   __atomic_store_n(&ctl->shutdown, 1, __ATOMIC_RELEASE);

@@ -125,10 +125,13 @@ def test_server_alone_and_in_mix(ctx):
     mix = mixed_requests(7, 30)
     st_probe = stage([probe, probe])
     st_mix = stage(mix)
-    B = Batch(ctx, max_slots=8)
+    # alone in a slot (slots_only), then in the mix of a default executor
+    B = Batch(ctx, max_slots=8, slots_only=True)
     t, fm = submit(B, probe, st_probe[0])
     st, r_alone, x_alone, m_alone, _ = collect(B, t, fm, probe.n)
+    B.close()
     assert st == 0
+    B = Batch(ctx, max_slots=8)
     handles = [submit(B, p, s) for p, s in zip(mix[:15], st_mix[:15])]
     tp, fp = submit(B, probe, st_probe[1])
     handles += [submit(B, p, s) for p, s in zip(mix[15:], st_mix[15:])]
@@ -143,7 +146,7 @@ def test_server_alone_and_in_mix(ctx):
     ref = oracle.project(probe.kind, probe.y, probe.A, probe.b, probe.lo, probe.hi, probe.C, probe.offsets)
     check(probe, x_mix, r_mix, ref, free_gpu=m_mix)
     assert all(o[0] == 0 for o in outs)
-    assert stats["completed"] == 32
+    assert stats["completed"] == 31
 
 
 def test_server_mix_parity(ctx):
@@ -186,7 +189,7 @@ def test_server_idle_exit_and_relaunch(ctx):
     p1 = I.compliance_3d(1, n=20000)
     p2 = I.multi_material(3, fields=4, n_per=5000)
     st_in = stage([p1, p2])
-    B = Batch(ctx, max_slots=4)
+    B = Batch(ctx, max_slots=4, slots_only=True)
     t, fm = submit(B, p1, st_in[0])
     assert collect(B, t, fm, p1.n)[0] == 0
     time.sleep(0.3)
@@ -214,13 +217,35 @@ def test_server_budget_backpressure(ctx):
     assert stats["peak_bytes"] <= 2 * fp
 
 
-def test_server_rejects_f64(ctx):
+def test_lone_request_full_gpu_route(ctx):
+    """A lone request (nothing else on the device) runs as one full-GPU launch
+    by default; the bits equal the slot route and a single launch."""
+    from paper_2511_13905_amd.api import Batch
+    p = I.multi_material(4, fields=4, n_per=40000)
+    say("lone route", p.n)
+    st_in = stage([p, p])
+    B = Batch(ctx, max_slots=8)
+    t, fm = submit(B, p, st_in[0])
+    a = collect(B, t, fm, p.n)
+    B.close()
+    B = Batch(ctx, max_slots=8, slots_only=True)
+    t, fm = submit(B, p, st_in[1])
+    b = collect(B, t, fm, p.n)
+    B.close()
+    xs, rs, ms = single(ctx, p)
+    assert a[0] == 0 and b[0] == 0
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[2], xs)
+    assert np.array_equal(a[3], b[3]) and np.array_equal(a[3], ms)
+
+
+@pytest.mark.parametrize("slots_only", [False, True])
+def test_server_rejects_f64(ctx, slots_only):
     from paper_2511_13905_amd.api import Batch
     from paper_2511_13905_amd import _native as N
     p = I.volume_2d(0)
     say("server f64 request")
     st_in = stage([p])
-    B = Batch(ctx, max_slots=2)
+    B = Batch(ctx, max_slots=2, slots_only=slots_only)
     t, fm = submit(B, p, st_in[0])
     st, r, _ = B.wait(t)
     B.close()
