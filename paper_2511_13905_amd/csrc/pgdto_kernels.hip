@@ -62,19 +62,52 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
-__device__ __forceinline__ void ld_vec(const T* __restrict__ p0, int64_t e0, int64_t n, bool full, T* o) {
+__device__ __forceinline__ void ld_vec_whole(const __attribute__((address_space(1))) T* p, int64_t e0, T* o) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) f32x4*>(p + e0);
+    o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+  } else {
+    const f64x2 q = *reinterpret_cast<const __attribute__((address_space(1))) f64x2*>(p + e0);
+    o[0] = q.x; o[1] = q.y;
+  }
+}
+
+// One vector slot: V elements from e0 (elements at or past n read as 0).
+template <typename T>
+__device__ __forceinline__ void ld_vec(const T* __restrict__ p0, int64_t e0, int64_t n, bool, T* o) {
+  constexpr int V = VT<T>::N;
   const auto p = gptr(p0);
-  if (full) {
-    if constexpr (sizeof(T) == 4) {
-      const f32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) f32x4*>(p + e0);
-      o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
-    } else {
-      const f64x2 q = *reinterpret_cast<const __attribute__((address_space(1))) f64x2*>(p + e0);
-      o[0] = q.x; o[1] = q.y;
-    }
+  if (e0 + V <= n) {
+    ld_vec_whole<T>(p, e0, o);
   } else {
 #pragma unroll
-    for (int k = 0; k < VT<T>::N; ++k) o[k] = (e0 + k < n) ? p[e0 + k] : (T)0;
+    for (int k = 0; k < V; ++k) o[k] = (e0 + k < n) ? p[e0 + k] : (T)0;
+  }
+}
+
+// K vector slots of NS streams at once.  When every lane of the wave has all
+// its K vectors inside the array (everywhere but near the array's end), one
+// wave-uniform branch issues the K x NS 16-byte loads back to back with no
+// other control flow, so they are all in flight together; a per-lane choice
+// between a vector load and element loads into the same registers would make
+// the compiler wait for each load before issuing the next.
+template <typename T, int K, int NS>
+__device__ __forceinline__ void ld_slots(const T* const* ptrs, const int64_t* e0, int64_t n,
+                                         T (&buf)[K][NS][VT<T>::N]) {
+  constexpr int V = VT<T>::N;
+  bool whole = true;
+#pragma unroll
+  for (int k = 0; k < K; ++k) whole = whole && (e0[k] + V <= n);
+  if (__all(whole)) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) ld_vec_whole<T>(gptr(ptrs[q]), e0[k], buf[k][q]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) ld_vec<T>(ptrs[q], e0[k], n, false, buf[k][q]);
   }
 }
 
@@ -416,12 +449,13 @@ __device__ __forceinline__ void stream_tile(const TileGeom& g, int64_t n, const 
     bool full[U], ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ok[u] = (k0 + u < g.nsweep) && slot<T>(g, k0 + u, e0[u], full[u], mask[u]);
-      if (ok[u]) {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) ld_vec<T>(ptrs[q], e0[u], n, full[u], buf[u][q]);
-      }
+      const bool live = k0 + u < g.nsweep;     // uniform over the block
+      ok[u] = live && slot<T>(g, k0 + u, e0[u], full[u], mask[u]);
+      if (!live) e0[u] = n;                    // reads zeros
     }
+    // every lane loads (a slot past the end reads zeros), so the loads of
+    // the whole chunk stay in flight together
+    ld_slots<T, U, NS>(ptrs, e0, n, buf);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) f(buf[u], e0[u], mask[u], full[u]);
@@ -790,13 +824,31 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         if (tile == wid && g.nsweep <= RS) {
           // load (pgd: form) this workgroup's first tile into registers
           const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+          {
+            int64_t re0[RS];
 #pragma unroll
-          for (int k = 0; k < RS; ++k) {
-            int64_t e0; bool full; uint32_t mask;
-            rslot(g, k, e0, full, mask);
-            if (!mask) continue;
-            ld_vec<T>(A, e0, d.n, full, ra[k]);
-            if (!d.pgd) ld_vec<T>(Y, e0, d.n, full, ry[k]);
+            for (int k = 0; k < RS; ++k) {
+              bool full; uint32_t mask;
+              rslot(g, k, re0[k], full, mask);
+              if (!mask) re0[k] = d.n;        // reads zeros
+            }
+            if (d.pgd) {
+              T tmp[RS][1][V];
+              const T* pa[1] = {A};
+              ld_slots<T, RS, 1>(pa, re0, d.n, tmp);
+#pragma unroll
+              for (int k = 0; k < RS; ++k)
+#pragma unroll
+                for (int q = 0; q < V; ++q) ra[k][q] = tmp[k][0][q];
+            } else {
+              T tmp[RS][2][V];
+              const T* pa[2] = {A, Y};
+              ld_slots<T, RS, 2>(pa, re0, d.n, tmp);
+#pragma unroll
+              for (int k = 0; k < RS; ++k)
+#pragma unroll
+                for (int q = 0; q < V; ++q) { ra[k][q] = tmp[k][0][q]; ry[k][q] = tmp[k][1][q]; }
+            }
           }
           if (d.pgd) {
             // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t
@@ -805,15 +857,21 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             // stored (the store may alias them)
             T nr[V], ng[V], nd[V];
             auto fetch = [&](int k) __attribute__((always_inline)) {
+              int64_t e0 = d.n;               // reads zeros
+              if (k < RS) {
+                bool full; uint32_t mask;
+                rslot(g, k, e0, full, mask);
+                if (!mask) e0 = d.n;
+              }
+              T tmp[1][3][V];
+              const T* pa[3] = {(const T*)d.rho, (const T*)d.grad, d.zero_step ? (const T*)d.rho : (const T*)d.dir};
+              ld_slots<T, 1, 3>(pa, &e0, d.n, tmp);
 #pragma unroll
-              for (int q = 0; q < V; ++q) nr[q] = ng[q] = nd[q] = (T)0;
-              if (k >= RS) return;
-              int64_t e0; bool full; uint32_t mask;
-              rslot(g, k, e0, full, mask);
-              if (!mask) return;
-              ld_vec<T>((const T*)d.rho, e0, d.n, full, nr);
-              ld_vec<T>((const T*)d.grad, e0, d.n, full, ng);
-              if (!d.zero_step) ld_vec<T>((const T*)d.dir, e0, d.n, full, nd);
+              for (int q = 0; q < V; ++q) {
+                nr[q] = tmp[0][0][q];
+                ng[q] = tmp[0][1][q];
+                nd[q] = d.zero_step ? (T)0 : tmp[0][2][q];
+              }
             };
             fetch(0);
 #pragma unroll
@@ -961,10 +1019,16 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           auto fetch_r = [&](int k) __attribute__((always_inline)) {
 #pragma unroll
             for (int q = 0; q < V; ++q) rnext[q] = (T)0;
-            if (d.pgd && k < RS && rmask(k)) {
-              int64_t e0; bool full; uint32_t mask;
+            if (d.pgd && k < RS) {
+              int64_t e0;
+              bool full; uint32_t mask;
               rslot(g, k, e0, full, mask);
-              ld_vec<T>(R, e0, d.n, full, rnext);
+              if (!rmask(k)) e0 = d.n;          // reads zeros
+              T tmp[1][1][V];
+              const T* pa[1] = {R};
+              ld_slots<T, 1, 1>(pa, &e0, d.n, tmp);
+#pragma unroll
+              for (int q = 0; q < V; ++q) rnext[q] = tmp[0][0][q];
             }
           };
           fetch_r(0);
@@ -989,12 +1053,15 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           auto fetch = [&](int k) __attribute__((always_inline)) {
             nany = (k < g.nsweep) && slot<T>(g, k, ne0, nfull, nmask);
             if (!nany) { nmask = 0u; ne0 = 0; nfull = false; }
+            int64_t le0 = nany ? ne0 : d.n;    // reads zeros
+            T tmp[1][3][V];
+            const T* pa[3] = {Y, A, d.pgd ? R : Y};
+            ld_slots<T, 1, 3>(pa, &le0, d.n, tmp);
 #pragma unroll
-            for (int q = 0; q < V; ++q) nr[q] = (T)0;
-            if (nany) {
-              ld_vec<T>(Y, ne0, d.n, nfull, ny);
-              ld_vec<T>(A, ne0, d.n, nfull, na);
-              if (d.pgd) ld_vec<T>(R, ne0, d.n, nfull, nr);
+            for (int q = 0; q < V; ++q) {
+              ny[q] = tmp[0][0][q];
+              na[q] = tmp[0][1][q];
+              nr[q] = d.pgd ? tmp[0][2][q] : (T)0;
             }
           };
           fetch(0);
@@ -1628,16 +1695,38 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         for (int j = 0; j < M; ++j) lamv[j] = sh.lamf[j];
         const T* R = (const T*)d.rho;
         const int lane = tid & 63;
+        // one slot ahead: y, the rows (and rho_t) of slot k + 1 are requested
+        // before x of slot k is stored (x may alias y)
+        constexpr int NF = M + 2;
+        const T* fp[NF];
+        fp[0] = Y;
+#pragma unroll
+        for (int j = 0; j < M; ++j) fp[1 + j] = Arow[j];
+        fp[M + 1] = d.pgd ? R : Y;
+        T nxt[1][NF][V];
+        auto fetch = [&](int k) __attribute__((always_inline)) {
+          int64_t e0 = d.n;                   // reads zeros
+          if (k < g.nsweep) {
+            bool full; uint32_t mask;
+            if (!slot<T>(g, k, e0, full, mask)) e0 = d.n;
+          }
+          ld_slots<T, 1, NF>(fp, &e0, d.n, nxt);
+        };
+        fetch(0);
         for (int k = 0; k < g.nsweep; ++k) {
           int64_t e0; bool full; uint32_t mask;
           const bool any = slot<T>(g, k, e0, full, mask);
+          T cur[NF][V];
+#pragma unroll
+          for (int q = 0; q < NF; ++q)
+#pragma unroll
+            for (int v = 0; v < V; ++v) cur[q][v] = nxt[0][q][v];
+          fetch(k + 1);
           uint32_t bits = 0;
           if (any) {
-            T yv[V], a[M][V], r[V];
-            ld_vec<T>(Y, e0, d.n, full, yv);
-#pragma unroll
-            for (int j = 0; j < M; ++j) ld_vec<T>(Arow[j], e0, d.n, full, a[j]);
-            if (d.pgd) ld_vec<T>(R, e0, d.n, full, r);
+            const T* yv = cur[0];
+            const T (*a)[V] = &cur[1];
+            const T* r = cur[M + 1];
             T xo[V];
 #pragma unroll
             for (int q = 0; q < V; ++q) {
