@@ -5,7 +5,7 @@
  * What it computes.  Every entry point solves the projection subproblem of the
  * paper: given a point y (the paper's rho~, the gradient step of Alg. 3), the
  * box [lo, hi] (the paper's [l, u]) and m linearized constraint rows
- * A x <= b (rows a_j = grad g_j(rho_t), Sec. 2.2, eq. (linearized)),
+ * A x <= b (rows a_j = grad g_j(rho_t), Sec. 3.2, eq. (linearized)),
  *
  *     x = argmin 1/2 ||x - y||^2 + (1/(2 kappa)) ||s||^2
  *         s.t. lo <= x <= hi,  A x - s <= b,  s >= 0,          kappa = 2/C
@@ -18,7 +18,7 @@
  *
  *   PGDTO_SINGLE       one dense row: Algorithm 1 (dual bracket search).
  *   PGDTO_INDEPENDENT  m rows on disjoint contiguous element ranges
- *                      (Sec. 2.2.2): one bracket search per block, all blocks
+ *                      (Sec. 3.2.2): one bracket search per block, all blocks
  *                      in one launch.
  *   PGDTO_COUPLED      m <= PGDTO_MAX_M dense rows: Algorithm 2 (Stage 1
  *                      single-active searches, then semismooth Newton with a
@@ -121,7 +121,7 @@ typedef struct {
 
 typedef struct {
   double tol_b;          /* bracket width at which a 1-D search stops (absolute,
-                            dual units; paper default 1e-8, Sec. 2.5)        */
+                            dual units; paper default 1e-8, Sec. 3.5)        */
   double tol_n;          /* residual tolerance relative to each row's scale
                             sigma_j = sum_i |a_ji| max(|lo|,|hi|); default
                             1e-12 (the paper's 1e-6 is absolute)             */
@@ -185,7 +185,7 @@ typedef struct {
 typedef struct pgdto_ctx pgdto_ctx;
 typedef struct pgdto_batch pgdto_batch;
 
-/* Defaults listed above (paper Sec. 2.5 where the paper fixes them). */
+/* Defaults listed above (paper Sec. 3.5 where the paper fixes them). */
 void pgdto_params_default(pgdto_params* p);
 void pgdto_pgd_args_default(pgdto_pgd_args* a);
 

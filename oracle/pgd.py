@@ -2,9 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Step size: Sec. 2.4.1 (eq. alpha, eq. final_alpha) with the first-step and
-fallback rule of Alg. 3 and Sec. 2.4.3 (alpha = min(alpha_max, alpha_fallback /
-||grad f||_inf)).  Direction: Sec. 2.4.2, eq. (CG), Polak-Ribiere with restart
+Step size: Sec. 3.4.1 (eq. alpha, eq. final_alpha) with the first-step and
+fallback rule of Alg. 3 and Sec. 3.4.3 (alpha = min(alpha_max, alpha_fallback /
+||grad f||_inf)).  Direction: Sec. 3.4.2, eq. (CG), Polak-Ribiere with restart
 (beta clipped at 0); Fletcher-Reeves and plain gradient are options.
 Constraint right-hand side: the linearized row g_j + a_j.(x - rho_t) <= G_j,
 i.e. b_j = G_j - g_j + a_j.rho_t (the paper's G-hat assumes rho~ = rho_t -
@@ -23,8 +23,8 @@ from .projection import fsum, project
 
 @dataclass
 class PgdParams:
-    """Defaults from Sec. 2.5 (C, alpha_max, tol_B, tol_N), Sec. 2.3 (alpha
-    fallback 0.2), Sec. 2.4.1 (eps_alpha 1e-6) and Sec. 2.4.3 (t_warmup 50,
+    """Defaults from Sec. 3.5 (C, alpha_max, tol_B, tol_N), Sec. 3.3 (alpha
+    fallback 0.2), Sec. 3.4.1 (eps_alpha 1e-6) and Sec. 3.4.3 (t_warmup 50,
     omega 1)."""
     alpha_max: float = 1e2
     alpha_fallback: float = 0.2

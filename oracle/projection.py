@@ -327,7 +327,7 @@ def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None):
 
     kind "single": one dense row (Algorithm 1's problem).
     kind "independent": disjoint blocks, A[i] is the coefficient of element i in
-        the row of the block that owns it (Sec. 2.2.2: separate 1-row problems).
+        the row of the block that owns it (Sec. 3.2.2: separate 1-row problems).
     kind "coupled": dense rows (Algorithm 2's problem)."""
     y = np.asarray(y, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64).reshape(-1)

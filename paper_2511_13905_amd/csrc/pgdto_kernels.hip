@@ -653,7 +653,7 @@ __device__ __forceinline__ void pgd_scalars(const Desc& d, const double* v, PgdS
 
 // ================================================================== 1-D kernel
 // SINGLE and INDEPENDENT: one bracket search per segment, all segments in
-// lockstep passes (Alg. 1; Sec. 2.2.2 for independent blocks).
+// lockstep passes (Alg. 1; Sec. 3.2.2 for independent blocks).
 
 struct Sh1D {
   double tot[PGDTO_MAX_BLOCKS * 8];

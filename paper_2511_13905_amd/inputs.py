@@ -1,9 +1,9 @@
 """Seeded synthetic problem generators.
 
 These build the inputs of the projection subproblem (the linearized problem of
-Sec. 2.2, eq. (linearized), and its regularized form, eq. (regularized_projection))
+Sec. 3.2, eq. (linearized), and its regularized form, eq. (regularized_projection))
 with the shapes, sizes and value distributions of the paper's four benchmark
-classes (Sec. 3.1: volume-constrained compliance, compliance-constrained volume,
+classes (Sec. 4.1: volume-constrained compliance, compliance-constrained volume,
 multi-material, volume + centre of mass).  The paper's own inputs come out of
 an FEA run, which is out of scope; these are stand-ins of the same structure.
 
@@ -25,7 +25,7 @@ import numpy as np
 
 LO = 1e-3          # x_min of the box [x_min, 1]
 HI = 1.0
-C_DEFAULT = 1e12   # the paper's default penalty C (Sec. 2.5 defaults)
+C_DEFAULT = 1e12   # the paper's default penalty C (Sec. 3.5 defaults)
 
 
 @dataclass
@@ -84,7 +84,7 @@ def _step_point(rng: np.random.Generator, n: int) -> np.ndarray:
 def volume_2d(seed: int, nx: int = 64, ny: int = 32, vf: float = 0.5,
               dtype=np.float64) -> Problem:
     """Single linear volume constraint sum(x)/n <= vf on an nx x ny grid
-    (Sec. 3.1.1, eq. (mincomp) with V_f).  64x32, float64 is the small case."""
+    (Sec. 4.1.1, eq. (mincomp) with V_f).  64x32, float64 is the small case."""
     n = nx * ny
     rng = np.random.default_rng(seed)
     y = _step_point(rng, n).astype(dtype)
@@ -123,7 +123,7 @@ def _lambda_for_free_fraction(y: np.ndarray, a: np.ndarray, frac: float,
 
 def compliance_3d(seed: int, shape=(256, 128, 128), free_frac: float = 0.4,
                   dtype=np.float32, n: int | None = None) -> Problem:
-    """Single linearized compliance constraint at scale (Sec. 3.1.2).
+    """Single linearized compliance constraint at scale (Sec. 4.1.2).
 
     a = dC/dx stand-in: -(|N(0,1)| + 0.01).  b is planted so that about
     ``free_frac`` of the elements are free at the solution.
@@ -143,7 +143,7 @@ def compliance_3d(seed: int, shape=(256, 128, 128), free_frac: float = 0.4,
 
 def multi_material(seed: int, fields: int = 4, n_per: int = 524288,
                    caps=(0.1, 0.1, 0.15, 0.15), dtype=np.float32) -> Problem:
-    """Independent per-material volume constraints (Sec. 3.1.3): ``fields``
+    """Independent per-material volume constraints (Sec. 4.1.3): ``fields``
     contiguous fields of ``n_per`` elements, sum_{i in M_j} x_i / n_per <= cap_j.
     4 x 524,288 (a 1024x512 grid per field), float32 is the at-scale case."""
     n = fields * n_per
@@ -159,7 +159,7 @@ def multi_material(seed: int, fields: int = 4, n_per: int = 524288,
 def volume_com(seed: int, grid=(192, 96, 96), vf: float = 0.3, target=(0.25, 0.25),
                band=(0.02, 0.01), feasible: bool | None = None, C: float = C_DEFAULT,
                dtype=np.float32) -> Problem:
-    """Coupled volume + centre-of-mass rows (Sec. 3.1.4), made linear.
+    """Coupled volume + centre-of-mass rows (Sec. 4.1.4), made linear.
 
     Domain [0,1] x [0,0.5] (x [0,0.5] in 3-D), element edge 1/nx, centroids at
     (i+1/2)/nx.  Rows: volume a = 1/n, b = vf; COM_x <= X_t + band_x and

@@ -24,7 +24,7 @@ def test_alg2_literal_reaches_the_certified_projection(seed):
 
 
 def test_alg2_literal_stage1_exit_on_single_active_row():
-    """If one row alone is active, Stage 1 returns it without Newton (Sec. 2.2.3)."""
+    """If one row alone is active, Stage 1 returns it without Newton (Sec. 3.2.3)."""
     rng = np.random.default_rng(2)
     n = 4000
     y = rng.uniform(-0.2, 1.2, n)

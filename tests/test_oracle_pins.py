@@ -119,7 +119,7 @@ def _random_case(rng, n, m, kind):
 @pytest.mark.parametrize("kind", ["random", "infeasible", "duplicate"])
 def test_brute_force_agrees(seed, m, kappa, kind):
     """Enumerating all element states and active row sets (Appendix A case
-    analysis) leaves exactly one x (uniqueness, Sec. 2.2.3), equal to the oracle's."""
+    analysis) leaves exactly one x (uniqueness, Sec. 3.2.3), equal to the oracle's."""
     if kind == "infeasible" and kappa == 0.0:
         pytest.skip("no KKT point exists without regularization")
     if kind == "infeasible" and kappa < 1e-6:
@@ -183,7 +183,7 @@ def test_planted_duals_recovered():
 
 
 def test_independent_blocks_equal_separate_solves():
-    """Disjoint index sets decouple into separate 1-row problems (Sec. 2.2.2)."""
+    """Disjoint index sets decouple into separate 1-row problems (Sec. 3.2.2)."""
     p = I.multi_material(2, fields=4, n_per=3000)
     r = oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, offsets=p.offsets)
     for j in range(4):
@@ -231,7 +231,7 @@ def test_permutation_equivariance():
 
 
 def test_regularization_limit():
-    """C -> infinity recovers the unregularized projection (Sec. 2.2.3)."""
+    """C -> infinity recovers the unregularized projection (Sec. 3.2.3)."""
     rng = np.random.default_rng(14)
     n = 4000
     y = rng.uniform(-0.2, 1.2, n)
