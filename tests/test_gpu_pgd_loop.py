@@ -114,13 +114,18 @@ def test_pgd_loop(ctx, kind, rule, steps):
         assert np.allclose(dn, ref["d"], rtol=1e-6, atol=1e-6 * np.max(np.abs(ref["d"]))), t
         prob = I.Problem(kind=kind, y=ref["rho_tilde"], A=A32, b=ref["b"], lo=lo, hi=hi, C=C)
         check(prob, xs, out["proj"], ref["proj"])
-        assert np.isclose(out["rel_change"], ref["rel_change"], rtol=1e-5), t
+        # the GPU measures |x - rho_t| / |x| on x rounded to float32: an absolute
+        # bar of a few float32 ulps once the iterates stagnate
+        assert np.isclose(out["rel_change"], ref["rel_change"], rtol=1e-5, atol=2.5e-7), t
+        assert out["converged"] == (out["rel_change"] <= hyper.tol)
         fallbacks.append(out["used_fallback"])
         rho_prev, grad_prev, rho = rho, gr, xs
         fvals.append(obj.value(rho.astype(np.float64)))
     assert fallbacks[0] and not all(fallbacks[1:])
     # the start point is infeasible for the coupled rows: compare from the first feasible iterate on
     assert fvals[-1] <= fvals[0]
-    assert min(fvals) >= fvals[-1] - 1e-6 * abs(fvals[-1])
+    if rule == "pr+":
+        # PR+ restarts keep the run settled at its best value (FR need not be monotone)
+        assert min(fvals) >= fvals[-1] - 1e-6 * abs(fvals[-1])
     viol = Ad @ rho.astype(np.float64) - G
     assert np.max(viol) <= 1e-5 * max(1.0, float(np.max(np.abs(G))))
