@@ -181,7 +181,7 @@ __device__ __forceinline__ void block_to_part(const double (&acc)[NV], int nv, u
 
 // Reduce the per-tile partials of every segment: tot[s * nv + v].  Every
 // workgroup runs this on the same data in the same order.
-__device__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const int32_t* tile_base,
+__device__ __forceinline__ void reduce_tiles(const double* pb, int nv, uint64_t maxmask, const int32_t* tile_base,
                              int nseg, double* tot) {
   constexpr int LMAX = 8;               // loads in flight per thread
   const int pairs = nseg * nv;
@@ -368,7 +368,7 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
 }
 
 // Workgroup 0 reports a timeout of this launch in the result.
-__device__ void report_error(const Desc& d, int32_t* err_field) {
+__device__ __forceinline__ void report_error(const Desc& d, int32_t* err_field) {
   if (wg_id(d) == 0 && threadIdx.x == 0 && err_field) {
     const SyncWords W = sync_words(d);
     if (__hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == d.epoch0)
@@ -480,7 +480,7 @@ struct Search {
 
 __device__ __forceinline__ bool inside(double v, double lo, double hi) { return v > lo && v < hi; }
 
-__device__ void search_pick(Search& S, int s, int mode, bool lean) {
+__device__ __forceinline__ void search_pick(Search& S, int s, int mode, bool lean) {
   const double lo = S.lo[s], hi = S.hi[s];
   const double mid = 0.5 * (lo + hi);
   if (mode == PGDTO_SEARCH_BISECT) {
@@ -518,7 +518,7 @@ __device__ void search_pick(Search& S, int s, int mode, bool lean) {
 // Initialise row/block s from the lam = 0 pass.  Returns true if the search
 // must run.  f0 = phi(0); s0 = -phi'(0); bp = largest breakpoint (the end of
 // Alg. 1's bracket, -y_l); ssat = a.x over the saturated point.
-__device__ bool search_init(Search& S, int s, double f0, double s0, double bp, double ssat,
+__device__ __forceinline__ bool search_init(Search& S, int s, double f0, double s0, double bp, double ssat,
                             double b, double kappa, double scale, int mode, bool lean) {
   S.npass[s] = 0;
   S.width[s] = 0.0;
@@ -555,7 +555,7 @@ __device__ bool search_init(Search& S, int s, double f0, double s0, double bp, d
 
 // Update row/block s from the sums of one search pass.  fsum[t] = a.x(trial_t),
 // ssum[t] = sum over free elements of a^2 at trial_t.
-__device__ void search_update(Search& S, int s, double f0sum, double f1sum, double s0sum, double s1sum,
+__device__ __forceinline__ void search_update(Search& S, int s, double f0sum, double f1sum, double s0sum, double s1sum,
                               double b, double kappa, double tol_n, double tol_b, int max_pass, int mode,
                               bool lean) {
   const double fsum[NT] = {f0sum, f1sum};
@@ -1260,7 +1260,7 @@ __device__ __forceinline__ void ncp(const double* h, const double* J, const doub
 // the paper NCP's h_j = 0 branch); active rows solve
 // (J + kappa I)_SS Delta_S = h_S - (J + kappa I)_SN Delta_N by Cholesky.
 template <int M>
-__device__ void newton_direction(const double* h, const double* J, const double* lam, double kappa,
+__device__ __forceinline__ void newton_direction(const double* h, const double* J, const double* lam, double kappa,
                                  const bool* act, const double* phi, int mode, double* delta) {
   double K[M][M], r[M];
 #pragma unroll
@@ -1329,7 +1329,7 @@ __device__ __forceinline__ double kkt_residual(const double* h, const double* la
 }
 
 template <int M>
-__device__ void set_trial(NewtonState& N) {
+__device__ __forceinline__ void set_trial(NewtonState& N) {
 #pragma unroll
   for (int j = 0; j < M; ++j) N.trial[j] = fmax(N.lam[j] + N.gamma * N.delta[j], 0.0);
 }
@@ -1337,7 +1337,7 @@ __device__ void set_trial(NewtonState& N) {
 // Accept (lam, h, J) as the current iterate; decide to stop or start a line
 // search.  Returns the next phase.
 template <int M>
-__device__ int newton_accept(ShC& sh, const double* lam, const double* h, const double* J) {
+__device__ __forceinline__ int newton_accept(ShC& sh, const double* lam, const double* h, const double* J) {
   NewtonState& N = sh.N;
   const CtlParams& d = sh.P;
 #pragma unroll
@@ -1380,7 +1380,7 @@ __device__ int newton_accept(ShC& sh, const double* lam, const double* h, const 
 // largest gamma in (0,1] with the Armijo condition (c1) and the curvature
 // condition (c2), searched by halving from 1).
 template <int M>
-__device__ int newton_after_trial(ShC& sh) {
+__device__ __forceinline__ int newton_after_trial(ShC& sh) {
   NewtonState& N = sh.N;
   const CtlParams& d = sh.P;
   const double* ht = N.ht;
@@ -1961,6 +1961,18 @@ union ShSrv {
   ShC sc;
 };
 
+// The server's shared state lives at namespace scope so that each solver
+// variant can be a separate (not inlined) function that still addresses LDS
+// directly: the register allocation of every variant then stays that of its
+// one-instance kernel instead of the maximum over all variants of one huge
+// function.
+__shared__ ShSrv srv_sh;
+__shared__ Desc srv_sd;
+
+__device__ __noinline__ void srv_solve_1d() { solve_1d<float>(srv_sh.s1, srv_sd); }
+template <int M>
+__device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd); }
+
 template <typename T>
 __device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
   if (!d.free_mask) return;
@@ -1974,8 +1986,7 @@ __device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
 
 __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
   __shared__ SrvArgs a;
-  __shared__ ShSrv sh;
-  __shared__ Desc sd;
+  Desc& sd = srv_sd;
   __shared__ int64_t job;
   __shared__ int32_t leave;
   {
@@ -2057,17 +2068,17 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
     clear_mask_tiles<float>(sd);
     if (sd.kind == PGDTO_COUPLED) {
       switch (sd.m) {
-        case 1: solve_coupled<float, 1>(sh.sc, sd); break;
-        case 2: solve_coupled<float, 2>(sh.sc, sd); break;
-        case 3: solve_coupled<float, 3>(sh.sc, sd); break;
-        case 4: solve_coupled<float, 4>(sh.sc, sd); break;
-        case 5: solve_coupled<float, 5>(sh.sc, sd); break;
-        case 6: solve_coupled<float, 6>(sh.sc, sd); break;
-        case 7: solve_coupled<float, 7>(sh.sc, sd); break;
-        default: solve_coupled<float, 8>(sh.sc, sd); break;
+        case 1: srv_solve_coupled<1>(); break;
+        case 2: srv_solve_coupled<2>(); break;
+        case 3: srv_solve_coupled<3>(); break;
+        case 4: srv_solve_coupled<4>(); break;
+        case 5: srv_solve_coupled<5>(); break;
+        case 6: srv_solve_coupled<6>(); break;
+        case 7: srv_solve_coupled<7>(); break;
+        default: srv_solve_coupled<8>(); break;
       }
     } else {
-      solve_1d<float>(sh.s1, sd);
+      srv_solve_1d();
     }
     __syncthreads();
     if (vb == 0 && threadIdx.x == 0) {
