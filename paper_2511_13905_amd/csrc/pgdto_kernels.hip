@@ -111,16 +111,19 @@ __device__ __forceinline__ void ld_slots(const T* const* ptrs, const int64_t* e0
   }
 }
 
+// Streamed outputs (x, d_t, a materialized rho~) are written with
+// non-temporal stores: they do not pile up as dirty lines in L2, which the
+// release at the end of every pass (an L2 write-back) would otherwise flush.
 template <typename T>
 __device__ __forceinline__ void st_vec(T* __restrict__ p0, int64_t e0, uint32_t mask, bool full, const T* v) {
   const auto p = gptr_w(p0);
   if (full) {
     if constexpr (sizeof(T) == 4) {
       const f32x4 q = {v[0], v[1], v[2], v[3]};
-      *reinterpret_cast<__attribute__((address_space(1))) f32x4*>(p + e0) = q;
+      __builtin_nontemporal_store(q, reinterpret_cast<__attribute__((address_space(1))) f32x4*>(p + e0));
     } else {
       const f64x2 q = {v[0], v[1]};
-      *reinterpret_cast<__attribute__((address_space(1))) f64x2*>(p + e0) = q;
+      __builtin_nontemporal_store(q, reinterpret_cast<__attribute__((address_space(1))) f64x2*>(p + e0));
     }
   } else {
 #pragma unroll
