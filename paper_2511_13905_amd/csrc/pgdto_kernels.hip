@@ -1211,7 +1211,6 @@ struct NewtonState {
   double trial[PGDTO_MAX_M], gamma;
   double blam[PGDTO_MAX_M], bh[PGDTO_MAX_M], bJ[PGDTO_MAX_M * PGDTO_MAX_M];  // best Armijo trial
   int32_t have_best, ls, it, init;   // init: next Newton pass is the starting evaluation
-  double ht[PGDTO_MAX_M], Jt[PGDTO_MAX_M * PGDTO_MAX_M];   // evaluation from the last pass
   double lam1[PGDTO_MAX_M];          // Stage-1 candidates
   double h0[PGDTO_MAX_M];
 };
@@ -1265,7 +1264,7 @@ __device__ __forceinline__ void ncp(const double* h, const double* J, const doub
 template <int M>
 __device__ __forceinline__ void newton_direction(const double* h, const double* J, const double* lam, double kappa,
                                  const bool* act, const double* phi, int mode, double* delta) {
-  double K[M][M], r[M];
+  double K[M][M], r[M], inv[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) delta[j] = act[j] ? 0.0 : (mode == PGDTO_NCP_PAPER ? phi[j] : -lam[j]);
 #pragma unroll
@@ -1292,12 +1291,13 @@ __device__ __forceinline__ void newton_direction(const double* h, const double* 
     for (int k = 0; k < j; ++k) dj -= K[j][k] * K[j][k];
     dj = dj > 0.0 ? sqrt(dj) : sqrt(fmax(kappa, 1e-300));
     K[j][j] = dj;
+    inv[j] = 1.0 / dj;                  // one division per pivot (a division is a long dependent chain)
 #pragma unroll
     for (int i = j + 1; i < M; ++i) {
       double v = K[i][j];
 #pragma unroll
       for (int k = 0; k < j; ++k) v -= K[i][k] * K[j][k];
-      K[i][j] = v / dj;
+      K[i][j] = v * inv[j];
     }
   }
 #pragma unroll
@@ -1305,14 +1305,14 @@ __device__ __forceinline__ void newton_direction(const double* h, const double* 
     double v = r[j];
 #pragma unroll
     for (int k = 0; k < j; ++k) v -= K[j][k] * r[k];
-    r[j] = v / K[j][j];
+    r[j] = v * inv[j];
   }
 #pragma unroll
   for (int j = M - 1; j >= 0; --j) {
     double v = r[j];
 #pragma unroll
     for (int k = j + 1; k < M; ++k) v -= K[k][j] * r[k];
-    r[j] = v / K[j][j];
+    r[j] = v * inv[j];
   }
 #pragma unroll
   for (int j = 0; j < M; ++j) if (act[j]) delta[j] = r[j];
@@ -1331,18 +1331,22 @@ __device__ __forceinline__ double kkt_residual(const double* h, const double* la
   return r;
 }
 
-template <int M>
-__device__ __forceinline__ void set_trial(NewtonState& N) {
-#pragma unroll
-  for (int j = 0; j < M; ++j) N.trial[j] = fmax(N.lam[j] + N.gamma * N.delta[j], 0.0);
-}
+// The Newton control runs on one thread over register copies: every LDS
+// value it needs is read up front (independent loads, one round trip) and
+// every result written once.  Working on the LDS state directly would cost a
+// dependent LDS round trip per access (several microseconds per step).
 
 // Accept (lam, h, J) as the current iterate; decide to stop or start a line
 // search.  Returns the next phase.
 template <int M>
-__device__ __forceinline__ int newton_accept(ShC& sh, const double* lam, const double* h, const double* J) {
+__device__ __forceinline__ int newton_accept(ShC& sh, const double (&lam)[M], const double (&h)[M],
+                                             const double (&J)[M * PGDTO_MAX_M]) {
   NewtonState& N = sh.N;
-  const CtlParams& d = sh.P;
+  double scale[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) scale[j] = sh.S.scale[j];
+  const double kappa = sh.P.kappa, tol_n = sh.P.tol_n;
+  const int ncp_mode = sh.P.ncp, max_newton = sh.P.max_newton, it = N.it;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     N.lam[j] = lam[j];
@@ -1350,52 +1354,56 @@ __device__ __forceinline__ int newton_accept(ShC& sh, const double* lam, const d
 #pragma unroll
     for (int k = 0; k < M; ++k) N.J[j * PGDTO_MAX_M + k] = J[j * PGDTO_MAX_M + k];
   }
-  const double res = kkt_residual<M>(N.h, N.lam, sh.S.scale);
+  const double res = kkt_residual<M>(h, lam, scale);
   sh.res_inf = res;
-  if (res <= d.tol_n) {
-    sh.outcome = PGDTO_CONVERGED;
-    for (int j = 0; j < M; ++j) sh.lamf[j] = N.lam[j];
+  if (res <= tol_n || it >= max_newton) {
+    sh.outcome = res <= tol_n ? PGDTO_CONVERGED : PGDTO_MAXITER;
+#pragma unroll
+    for (int j = 0; j < M; ++j) sh.lamf[j] = lam[j];
     return PH_FINAL;
   }
-  if (N.it >= d.max_newton) {
-    sh.outcome = PGDTO_MAXITER;
-    for (int j = 0; j < M; ++j) sh.lamf[j] = N.lam[j];
-    return PH_FINAL;
-  }
-  double phi[M];
+  double phi[M], delta[M];
   bool act[M];
-  ncp<M>(N.h, N.J, N.lam, d.kappa, d.ncp, phi, act);
+  ncp<M>(h, J, lam, kappa, ncp_mode, phi, act);
   double p2 = 0.0;
 #pragma unroll
   for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
+  newton_direction<M>(h, J, lam, kappa, act, phi, ncp_mode, delta);
   N.phi2 = p2;
   N.M0 = 0.5 * p2;
-  newton_direction<M>(N.h, N.J, N.lam, d.kappa, act, phi, d.ncp, N.delta);
   N.gamma = 1.0;
   N.ls = 0;
   N.have_best = 0;
-  N.it += 1;
-  set_trial<M>(N);
+  N.it = it + 1;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    N.delta[j] = delta[j];
+    N.trial[j] = fmax(lam[j] + delta[j], 0.0);
+  }
   return PH_NEWTON;
 }
 
-// Line-search decision after evaluating the trial (Appendix A.2: the
-// largest gamma in (0,1] with the Armijo condition (c1) and the curvature
+// Line-search decision after evaluating the trial (tr, ht, Jt) (Appendix A.2:
+// the largest gamma in (0,1] with the Armijo condition (c1) and the curvature
 // condition (c2), searched by halving from 1).
 template <int M>
-__device__ __forceinline__ int newton_after_trial(ShC& sh) {
+__device__ __forceinline__ int newton_after_trial(ShC& sh, const double (&tr)[M], const double (&ht)[M],
+                                                  const double (&Jt)[M * PGDTO_MAX_M]) {
   NewtonState& N = sh.N;
-  const CtlParams& d = sh.P;
-  const double* ht = N.ht;
-  const double* Jt = N.Jt;
+  double delta[M], lam[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) { delta[j] = N.delta[j]; lam[j] = N.lam[j]; }
+  const double kappa = sh.P.kappa, c1 = sh.P.c1, c2 = sh.P.c2;
+  const int ncp_mode = sh.P.ncp, max_ls = sh.P.max_ls;
+  const double M0 = N.M0, phi2 = N.phi2, gamma = N.gamma;
+  const int have_best = N.have_best, ls = N.ls + 1;
   double phi[M];
   bool act[M];
-  ncp<M>(ht, Jt, N.trial, d.kappa, d.ncp, phi, act);
+  ncp<M>(ht, Jt, tr, kappa, ncp_mode, phi, act);
   double p2 = 0.0;
 #pragma unroll
   for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
-  const double Mt = 0.5 * p2;
-  const bool armijo = Mt <= N.M0 - d.c1 * N.gamma * N.phi2;
+  const bool armijo = 0.5 * p2 <= M0 - c1 * gamma * phi2;
   // grad M(trial)^T Delta = Phi_t^T J_Phi(trial) Delta
   double g = 0.0;
 #pragma unroll
@@ -1404,32 +1412,44 @@ __device__ __forceinline__ int newton_after_trial(ShC& sh) {
     if (act[j]) {
       row = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) row += (Jt[j * PGDTO_MAX_M + k] + (j == k ? d.kappa : 0.0)) * N.delta[k];
+      for (int k = 0; k < M; ++k) row += (Jt[j * PGDTO_MAX_M + k] + (j == k ? kappa : 0.0)) * delta[k];
     } else {
-      row = (d.ncp == PGDTO_NCP_PAPER) ? N.delta[j] : (Jt[j * PGDTO_MAX_M + j] + d.kappa) * N.delta[j];
+      row = (ncp_mode == PGDTO_NCP_PAPER) ? delta[j] : (Jt[j * PGDTO_MAX_M + j] + kappa) * delta[j];
     }
     g += phi[j] * row;
   }
-  const bool curv = g <= d.c2 * N.phi2;
-  N.ls += 1;
-  sh.N.init = 0;
-  if (armijo && !N.have_best) {
+  const bool curv = g <= c2 * phi2;
+  N.ls = ls;
+  N.init = 0;
+  if (armijo && !have_best) {
     N.have_best = 1;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      N.blam[j] = N.trial[j];
+      N.blam[j] = tr[j];
       N.bh[j] = ht[j];
 #pragma unroll
       for (int k = 0; k < M; ++k) N.bJ[j * PGDTO_MAX_M + k] = Jt[j * PGDTO_MAX_M + k];
     }
   }
-  if (armijo && curv) return newton_accept<M>(sh, N.trial, ht, Jt);
-  if (N.ls >= d.max_ls) {
-    if (N.have_best) return newton_accept<M>(sh, N.blam, N.bh, N.bJ);
-    return newton_accept<M>(sh, N.trial, ht, Jt);
+  if (armijo && curv) return newton_accept<M>(sh, tr, ht, Jt);
+  if (ls >= max_ls) {
+    if (have_best) {
+      double bl[M], bh[M], bJ[M * PGDTO_MAX_M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        bl[j] = N.blam[j];
+        bh[j] = N.bh[j];
+#pragma unroll
+        for (int k = 0; k < M; ++k) bJ[j * PGDTO_MAX_M + k] = N.bJ[j * PGDTO_MAX_M + k];
+      }
+      return newton_accept<M>(sh, bl, bh, bJ);
+    }
+    return newton_accept<M>(sh, tr, ht, Jt);
   }
-  N.gamma *= 0.5;
-  set_trial<M>(N);
+  const double gnew = 0.5 * gamma;
+  N.gamma = gnew;
+#pragma unroll
+  for (int j = 0; j < M; ++j) N.trial[j] = fmax(lam[j] + gnew * delta[j], 0.0);
   return PH_NEWTON;
 }
 
@@ -1860,9 +1880,13 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         } else {
           sh.path = 3;
           if (C::FUSE) {
-            for (int j = 0; j < M; ++j) sh.N.ht[j] = t[M * M + j] - sh.bs[j] - kappa * sh.N.lam1[j];
-            unpack_J<M>(&t[M * M + M], sh.N.Jt);
-            sh.phase = newton_accept<M>(sh, sh.N.lam1, sh.N.ht, sh.N.Jt);
+            double l1[M], ht[M], Jt[M * PGDTO_MAX_M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) l1[j] = sh.N.lam1[j];
+#pragma unroll
+            for (int j = 0; j < M; ++j) ht[j] = t[M * M + j] - sh.bs[j] - kappa * l1[j];
+            unpack_J<M>(&t[M * M + M], Jt);
+            sh.phase = newton_accept<M>(sh, l1, ht, Jt);
           } else {
             for (int j = 0; j < M; ++j) sh.N.trial[j] = sh.N.lam1[j];
             sh.N.init = 1;
@@ -1874,13 +1898,18 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
       if (tid == 0) {
         sh.passes += 1;
         ls_total += 1;
-        for (int j = 0; j < M; ++j) sh.N.ht[j] = t[j] - sh.bs[j] - kappa * sh.N.trial[j];
-        unpack_J<M>(&t[M], sh.N.Jt);
+        // the evaluated trial, its h and J, in registers
+        double tr[M], ht[M], Jt[M * PGDTO_MAX_M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) tr[j] = sh.N.trial[j];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ht[j] = t[j] - sh.bs[j] - kappa * tr[j];
+        unpack_J<M>(&t[M], Jt);
         if (sh.N.init) {
           sh.N.init = 0;
-          sh.phase = newton_accept<M>(sh, sh.N.trial, sh.N.ht, sh.N.Jt);
+          sh.phase = newton_accept<M>(sh, tr, ht, Jt);
         } else {
-          sh.phase = newton_after_trial<M>(sh);
+          sh.phase = newton_after_trial<M>(sh, tr, ht, Jt);
         }
       }
     } else {  // PH_FINAL
