@@ -213,7 +213,7 @@ int pgdto_pgd_step(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_param
 int pgdto_pgd_step_async(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,
                          pgdto_pgd_out* out_dev, void* stream);
 
-/* Serving: continuous batching of projection requests.
+/* Serving: continuous batching of projection and Algorithm 3 requests.
  *
  * max_slots != 1 selects the persistent executor: one long-running
  * cooperative launch whose workgroups form max_slots slots; each slot solves
@@ -246,6 +246,13 @@ int pgdto_batch_create(pgdto_ctx* ctx, const pgdto_batch_cfg* cfg, pgdto_batch**
  * cleared by the caller.  Host arrays are copied. */
 int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, const pgdto_params* params,
                        uint64_t* ticket);
+/* An Algorithm 3 step (as pgdto_pgd_step) as a served request: the same
+ * contract as pgdto_batch_submit for its device buffers (rho_t, rho_{t-1},
+ * grad, grad_{t-1}, d: read; d and x: written; all ready at submit and kept
+ * valid until the ticket retires); g, G and block offsets are copied.  Poll it
+ * with pgdto_batch_poll_pgd (pgdto_batch_poll returns its projection part). */
+int pgdto_batch_submit_pgd(pgdto_batch* b, const pgdto_pgd_args* args, const pgdto_params* params,
+                           uint64_t* ticket);
 /* PGDTO_QUEUED / PGDTO_PENDING / PGDTO_OK (result copied, ticket retired) /
  * error.  Thread-safe. */
 int pgdto_batch_poll(pgdto_batch* b, uint64_t ticket, pgdto_result* out);
@@ -255,6 +262,9 @@ int pgdto_batch_wait(pgdto_batch* b, uint64_t ticket, pgdto_result* out);
  * returns, when the ticket retires, times[0..2] = submitted, admitted to the
  * device, completion seen, in ns on the host's monotonic clock. */
 int pgdto_batch_poll_timed(pgdto_batch* b, uint64_t ticket, pgdto_result* out, int64_t* times, int wait);
+/* pgdto_batch_poll_timed for any ticket, returning the whole Algorithm 3
+ * output (a projection ticket fills out->proj only).  times may be NULL. */
+int pgdto_batch_poll_pgd(pgdto_batch* b, uint64_t ticket, pgdto_pgd_out* out, int64_t* times, int wait);
 /* Executor shape: slots and workgroups per slot (0, 0 on the plain path). */
 int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot);
 /* Statistics: admitted, completed, queued, in flight, peak footprint. */

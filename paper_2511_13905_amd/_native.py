@@ -106,6 +106,8 @@ SIGNATURES = {
     "pgdto_batch_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result)]),
     "pgdto_batch_wait": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result)]),
     "pgdto_batch_poll_timed": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result), C.POINTER(C.c_int64), C.c_int]),
+    "pgdto_batch_submit_pgd": (C.c_int, [_VP, C.POINTER(PgdArgs), C.POINTER(Params), C.POINTER(C.c_uint64)]),
+    "pgdto_batch_poll_pgd": (C.c_int, [_VP, C.c_uint64, C.POINTER(PgdOut), C.POINTER(C.c_int64), C.c_int]),
     "pgdto_batch_shape": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pgdto_batch_stats": (C.c_int, [_VP] + [C.POINTER(C.c_int64)] * 5),
     "pgdto_batch_destroy": (C.c_int, [_VP]),

@@ -170,9 +170,9 @@ class Context:
 
     # ------------------------------------------------------------ Alg. 3 step
     def _pgd_struct(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                    hyper, keep):
+                    hyper, keep, copy_ok=True):
         s, x, _A = problem_struct(kind, None, A, None, lo, hi, C, offsets, x if x is not None else
-                                  torch.empty_like(rho), None, keep)
+                                  torch.empty_like(rho), None, keep, copy_ok=copy_ok)
         a = N.PgdArgs()
         N.lib().pgdto_pgd_args_default(C_byref(a))
         a.proj = s
@@ -267,6 +267,30 @@ class Batch:
         _check(N.lib().pgdto_batch_submit(self.h, C_byref(s), C_byref(p), C_byref(t)), "pgdto_batch_submit")
         self._live[t.value] = (y, A_used, x, free_mask)
         return t.value
+
+    def submit_pgd(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf, offsets=None,
+                   x=None, params=None, **hyper) -> int:
+        """pgdto_batch_submit_pgd: one Algorithm 3 step as a served request
+        (d is updated in place, rho_{t+1} lands in x).  A must already have
+        16-byte aligned rows; the data must be complete when this is called."""
+        keep = _Keep()
+        a, x = self.ctx._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
+                                    hyper, keep, copy_ok=False)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        tk = C_u64()
+        _check(N.lib().pgdto_batch_submit_pgd(self.h, C_byref(a), C_byref(p), C_byref(tk)), "pgdto_batch_submit_pgd")
+        self._live[tk.value] = (rho, A, x, rho_prev, grad, grad_prev, d)
+        return tk.value
+
+    def poll_pgd(self, ticket, wait=False):
+        """(status, Algorithm 3 output dict or None, times or None)."""
+        out = N.PgdOut()
+        times = (C.c_int64 * 3)()
+        st = N.lib().pgdto_batch_poll_pgd(self.h, ticket, C_byref(out), times, 1 if wait else 0)
+        if st in (N.QUEUED, N.PENDING):
+            return st, None, None
+        self._live.pop(ticket, None)
+        return st, out.to_dict(), (times[0], times[1], times[2])
 
     def x_of(self, ticket):
         return self._live[ticket][2]

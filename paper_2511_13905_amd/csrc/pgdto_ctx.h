@@ -21,5 +21,6 @@ struct pgdto_ctx {
 namespace pgdto {
 int validate_params(const pgdto_params* p);
 int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Desc& d);
+int fill_pgd(const pgdto_pgd_args* a, Desc& d);
 int grid_for(pgdto_ctx* c, const Desc& d);
 }  // namespace pgdto

@@ -97,7 +97,7 @@ struct SrvArgs {
   SrvHostCtl* ctl;             // pinned
   const Desc* jobs;            // pinned [qcap]: job j at j % qcap
   uint64_t* done;              // pinned [qcap]: j + 1 once job j finished
-  pgdto_result* results;       // pinned [qcap]
+  pgdto_pgd_out* results;      // pinned [qcap] (a projection fills .proj)
   uint64_t* head;              // device: next job to claim
   uint64_t* slot_words;        // device: [slots][16]: broadcast sequence, job index
   double* part;                // device: per-slot partial sums, stride part_stride

@@ -1982,8 +1982,9 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
 // the slot, every workgroup of the slot copies the job's descriptor, clears
 // the free-mask words of its tiles and runs the same solver as a one-instance
 // launch on W workgroups, with the slot's own partial sums and barrier words.
-// Results are bitwise those of a one-instance launch: the reduction order
-// follows the tiles, which depend only on n and the dtype.  A slot leaves
+// Jobs are projections or Algorithm 3 steps.  Results are bitwise those of a
+// one-instance launch: the reduction order follows the tiles, which depend
+// only on n and the dtype.  A slot leaves
 // when the host sets shutdown and no job is left, or after idle_spins polls
 // without a job (the host launches the kernel again when new work comes).
 // float32 streams only.
@@ -2091,9 +2092,8 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
         sd.wg_count = W;
         sd.part = a.part + (size_t)slot * a.part_stride;
         sd.sync = a.sync + (size_t)slot * a.sync_stride;
-        sd.result = a.results + q;
+        sd.result = sd.pgd ? (void*)(a.results + q) : (void*)&a.results[q].proj;
         sd.trace = nullptr;
-        sd.pgd = 0;
       }
       __syncthreads();
     }

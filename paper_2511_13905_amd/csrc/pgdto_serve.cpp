@@ -38,6 +38,37 @@ size_t request_footprint(const pgdto_problem& p) {
   return esz * n * (rows + 2);
 }
 
+pgdto_problem Request::problem() const {
+  pgdto_problem p = pgd ? args.proj : prob;
+  p.b = pgd ? nullptr : b;
+  p.block_offsets = p.kind == PGDTO_INDEPENDENT ? off : nullptr;
+  return p;
+}
+
+pgdto_pgd_args Request::pgd_args() const {
+  pgdto_pgd_args a = args;
+  a.proj = problem();
+  a.g = g;
+  a.G = G;
+  return a;
+}
+
+// Host-side validation and the launch descriptor of a request (the same
+// checks as pgdto_project / pgdto_pgd_step).
+int build_request_desc(const Request& r, Desc& d) {
+  if (!r.pgd) {
+    const pgdto_problem p = r.problem();
+    return build_desc(&p, &r.params, true, d);
+  }
+  const pgdto_pgd_args a = r.pgd_args();
+  pgdto_problem pr = a.proj;
+  double zeros[PGDTO_MAX_BLOCKS] = {0};   // b is formed on the device
+  pr.b = zeros;
+  int st = build_desc(&pr, &r.params, false, d);
+  if (st != PGDTO_OK) return st;
+  return fill_pgd(&a, d);
+}
+
 }  // namespace pgdto
 
 using namespace pgdto;
@@ -91,20 +122,62 @@ extern "C" int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, con
   return b->submit(r, ticket);
 }
 
+extern "C" int pgdto_batch_submit_pgd(pgdto_batch* b, const pgdto_pgd_args* args, const pgdto_params* params,
+                                      uint64_t* ticket) {
+  if (!b || !args || !ticket || !args->g || !args->G) return PGDTO_ERR_ARG;
+  const pgdto_problem* prob = &args->proj;
+  if (prob->m < 1 || prob->m > PGDTO_MAX_BLOCKS) return PGDTO_ERR_ARG;
+  if (prob->kind == PGDTO_INDEPENDENT && !prob->block_offsets) return PGDTO_ERR_ARG;
+  Request r;
+  if (params) r.params = *params; else pgdto_params_default(&r.params);
+  r.pgd = 1;
+  r.args = *args;
+  r.m = prob->m;
+  for (int j = 0; j < prob->m; ++j) { r.g[j] = args->g[j]; r.G[j] = args->G[j]; }
+  if (prob->kind == PGDTO_INDEPENDENT)
+    for (int j = 0; j <= prob->m; ++j) r.off[j] = prob->block_offsets[j];
+  r.args.proj.b = nullptr;
+  r.args.proj.block_offsets = nullptr;
+  r.args.g = nullptr;
+  r.args.G = nullptr;
+  Desc d;
+  int st = build_request_desc(r, d);        // validate now (host only)
+  if (st != PGDTO_OK) return st;
+  const size_t esz = prob->dtype == PGDTO_F32 ? 4 : 8;
+  r.footprint = request_footprint(*prob) + esz * (size_t)prob->n * 5;   // + rho, rho_prev, grad, grad_prev, d
+  if (r.footprint > b->cfg.hbm_budget_bytes) return PGDTO_ERR_NOMEM;
+  return b->submit(r, ticket);
+}
+
+static int poll_result(pgdto_batch* b, uint64_t ticket, pgdto_result* out, int64_t* times, bool wait) {
+  pgdto_pgd_out o;
+  int is_pgd = 0;
+  const int st = b->poll(ticket, &o, wait, times, &is_pgd);
+  if (st == PGDTO_OK || st < 0) *out = o.proj;
+  return st;
+}
+
 extern "C" int pgdto_batch_poll(pgdto_batch* b, uint64_t ticket, pgdto_result* out) {
   if (!b || !out) return PGDTO_ERR_ARG;
-  return b->poll(ticket, out, false);
+  return poll_result(b, ticket, out, nullptr, false);
 }
 
 extern "C" int pgdto_batch_wait(pgdto_batch* b, uint64_t ticket, pgdto_result* out) {
   if (!b || !out) return PGDTO_ERR_ARG;
-  return b->poll(ticket, out, true);
+  return poll_result(b, ticket, out, nullptr, true);
 }
 
 extern "C" int pgdto_batch_poll_timed(pgdto_batch* b, uint64_t ticket, pgdto_result* out, int64_t* times,
                                       int wait) {
   if (!b || !out || !times) return PGDTO_ERR_ARG;
-  return b->poll(ticket, out, wait != 0, times);
+  return poll_result(b, ticket, out, times, wait != 0);
+}
+
+extern "C" int pgdto_batch_poll_pgd(pgdto_batch* b, uint64_t ticket, pgdto_pgd_out* out, int64_t* times,
+                                    int wait) {
+  if (!b || !out) return PGDTO_ERR_ARG;
+  int is_pgd = 0;
+  return b->poll(ticket, out, wait != 0, times, &is_pgd);
 }
 
 extern "C" int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot) {
@@ -144,21 +217,22 @@ int pgdto_batch::submit(const Request& r0, uint64_t* ticket) {
   Request r = r0;
   r.ticket = next_ticket++;
   r.state = PGDTO_QUEUED;
-  records[r.ticket] = Record{PGDTO_QUEUED, {}, clock_ns(), 0, 0};
+  records[r.ticket] = Record{PGDTO_QUEUED, {}, clock_ns(), 0, 0, r.pgd};
   queue.push_back(r);
   *ticket = r.ticket;
   cv.notify_all();
   return PGDTO_OK;
 }
 
-int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait, int64_t* times) {
+int pgdto_batch::poll(uint64_t ticket, pgdto_pgd_out* out, bool wait, int64_t* times, int* is_pgd) {
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     auto it = records.find(ticket);
     if (it == records.end()) return PGDTO_ERR_UNKNOWN_TICKET;
     const int st = it->second.state;
+    if (is_pgd) *is_pgd = it->second.pgd;
     if (st == PGDTO_OK || st < 0) {
-      *out = it->second.result;
+      *out = it->second.out;
       if (times) {
         times[0] = it->second.t_submit;
         times[1] = it->second.t_start;
@@ -172,13 +246,13 @@ int pgdto_batch::poll(uint64_t ticket, pgdto_result* out, bool wait, int64_t* ti
   }
 }
 
-void pgdto_batch::finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint, int64_t t_start,
+void pgdto_batch::finish(uint64_t ticket, int status, const pgdto_pgd_out& res, size_t footprint, int64_t t_start,
                          int64_t t_done) {
   std::lock_guard<std::mutex> lk(mu);
   auto it = records.find(ticket);
   if (it != records.end()) {
     it->second.state = status;
-    it->second.result = res;
+    it->second.out = res;
     it->second.t_start = t_start;
     it->second.t_done = t_done;
   }
@@ -211,7 +285,7 @@ void pgdto_batch::cancel_queued() {
     auto it = records.find(r.ticket);
     if (it != records.end()) {
       it->second.state = PGDTO_ERR_CANCELLED;
-      memset(&it->second.result, 0, sizeof(pgdto_result));
+      memset(&it->second.out, 0, sizeof(pgdto_pgd_out));
     }
   }
   queue.clear();
@@ -229,14 +303,18 @@ void pgdto_batch::run_plain() {
       if (stopping && queue.empty()) return;
       if (!pop_admissible(r, 1)) continue;
     }
-    pgdto_problem p = r.prob;
-    p.b = r.b;
-    p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
-    pgdto_result res;
+    pgdto_pgd_out res;
     memset(&res, 0, sizeof(res));
     const int64_t t0 = clock_ns();
-    int st = pgdto_project(plain_ctx, &p, &r.params, &res, (void*)plain_stream);
-    if (st == PGDTO_OK && res.error != 0) st = res.error;
+    int st;
+    if (r.pgd) {
+      const pgdto_pgd_args a = r.pgd_args();
+      st = pgdto_pgd_step(plain_ctx, &a, &r.params, &res, (void*)plain_stream);
+    } else {
+      const pgdto_problem p = r.problem();
+      st = pgdto_project(plain_ctx, &p, &r.params, &res.proj, (void*)plain_stream);
+    }
+    if (st == PGDTO_OK && res.proj.error != 0) st = res.proj.error;
     finish(r.ticket, st, res, r.footprint, t0, clock_ns());
   }
 }

@@ -22,15 +22,26 @@ struct Request {
   double b[PGDTO_MAX_BLOCKS] = {};
   int64_t off[PGDTO_MAX_BLOCKS + 1] = {};
   size_t footprint = 0;
+  // an Algorithm 3 step instead of a projection (pgd != 0): args with its
+  // host arrays (g, G, block offsets) pointing into this request
+  int pgd = 0;
+  pgdto_pgd_args args{};
+  double g[PGDTO_MAX_BLOCKS] = {}, G[PGDTO_MAX_BLOCKS] = {};
+
+  // the problem / step arguments with their host arrays bound to this copy
+  pgdto_problem problem() const;
+  pgdto_pgd_args pgd_args() const;
 };
 
 struct Record {
   int state;                 // PGDTO_QUEUED / PGDTO_PENDING / PGDTO_OK / error
-  pgdto_result result;
+  pgdto_pgd_out out;         // projections use out.proj only
   int64_t t_submit, t_start, t_done;   // host monotonic clock, ns
+  int pgd;
 };
 
 size_t request_footprint(const pgdto_problem& p);
+int build_request_desc(const Request& r, Desc& d);   // validation + descriptor (host only)
 
 struct Server;   // slot-based persistent executor (pgdto_server.cpp)
 
@@ -58,8 +69,8 @@ struct pgdto_batch {
   int start();
   void stop();
   int submit(const pgdto::Request& r, uint64_t* ticket);
-  int poll(uint64_t ticket, pgdto_result* out, bool wait, int64_t* times = nullptr);
-  void finish(uint64_t ticket, int status, const pgdto_result& res, size_t footprint, int64_t t_start,
+  int poll(uint64_t ticket, pgdto_pgd_out* out, bool wait, int64_t* times, int* is_pgd);
+  void finish(uint64_t ticket, int status, const pgdto_pgd_out& res, size_t footprint, int64_t t_start,
               int64_t t_done);
   bool pop_admissible(pgdto::Request& r, size_t slots_free);
   void cancel_queued();

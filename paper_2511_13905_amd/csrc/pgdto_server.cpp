@@ -40,7 +40,7 @@ struct Server {
   SrvHostCtl* ctl = nullptr;     // pinned
   Desc* jobs = nullptr;          // pinned [qcap]
   uint64_t* done = nullptr;      // pinned [qcap]
-  pgdto_result* results = nullptr;   // pinned [qcap]
+  pgdto_pgd_out* results = nullptr;  // pinned [qcap]
   uint64_t* head = nullptr;      // device
   uint64_t* slot_words = nullptr;    // device
   double* part = nullptr;        // device
@@ -51,7 +51,7 @@ struct Server {
   pgdto_ctx* os_ctx = nullptr;
   hipStream_t os_stream = nullptr;
   hipEvent_t os_event = nullptr;
-  pgdto_result* os_res = nullptr;    // pinned
+  pgdto_pgd_out* os_res = nullptr;   // pinned
   bool os_busy = false;
   uint64_t os_ticket = 0;
   size_t os_footprint = 0;
@@ -92,7 +92,7 @@ int Server::init() {
   ok = ok && hipHostMalloc((void**)&ctl, sizeof(SrvHostCtl), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&jobs, sizeof(Desc) * qcap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&done, sizeof(uint64_t) * qcap, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&results, sizeof(pgdto_result) * qcap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&results, sizeof(pgdto_pgd_out) * qcap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMalloc(&head, 256) == hipSuccess;
   ok = ok && hipMalloc(&slot_words, sizeof(uint64_t) * 16 * slots) == hipSuccess;
   ok = ok && hipMalloc(&part, sizeof(double) * PART_DOUBLES * slots) == hipSuccess;
@@ -100,13 +100,13 @@ int Server::init() {
   ok = ok && hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&os_stream, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&os_event, hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&os_res, sizeof(pgdto_result), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&os_res, sizeof(pgdto_pgd_out), hipHostMallocDefault) == hipSuccess;
   ok = ok && pgdto_ctx_create(b->ctx->device, &os_ctx) == PGDTO_OK;
   if (!ok) return PGDTO_ERR_NOMEM;
   memset(ctl, 0, sizeof(SrvHostCtl));
   memset(jobs, 0, sizeof(Desc) * qcap);
   memset(done, 0, sizeof(uint64_t) * qcap);
-  memset(results, 0, sizeof(pgdto_result) * qcap);
+  memset(results, 0, sizeof(pgdto_pgd_out) * qcap);
   ok = ok && hipMemset(head, 0, 256) == hipSuccess;
   ok = ok && hipMemset(slot_words, 0, sizeof(uint64_t) * 16 * slots) == hipSuccess;
   ok = ok && hipMemset(sync, 0, sizeof(uint64_t) * SYNC_WORDS * slots) == hipSuccess;
@@ -139,12 +139,12 @@ bool Server::oneshot() {
     const hipError_t q = hipEventQuery(os_event);
     if (q == hipErrorNotReady) return false;
     os_busy = false;
-    pgdto_result r = *os_res;
-    int st = q == hipSuccess ? (r.error != 0 ? r.error : PGDTO_OK) : PGDTO_ERR_HIP;
+    pgdto_pgd_out r = *os_res;
+    int st = q == hipSuccess ? (r.proj.error != 0 ? r.proj.error : PGDTO_OK) : PGDTO_ERR_HIP;
     if (q != hipSuccess) {
       (void)hipGetLastError();
       memset(&r, 0, sizeof(r));
-      r.error = PGDTO_ERR_HIP;
+      r.proj.error = PGDTO_ERR_HIP;
     }
     b->finish(os_ticket, st, r, os_footprint, os_t_start, now_ns());
     return true;
@@ -159,25 +159,30 @@ bool Server::oneshot() {
   // slots exit at their next poll of an empty queue); the full-GPU launch
   // starts right after it in device order
   if (running) __atomic_store_n(&ctl->shutdown, 1, __ATOMIC_RELEASE);
-  pgdto_problem p = r.prob;
-  p.b = r.b;
-  p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
+  const pgdto_problem p = r.problem();
   if (p.dtype != PGDTO_F32) {       // the persistent executor takes float32 only, on either route
-    pgdto_result res;
+    pgdto_pgd_out res;
     memset(&res, 0, sizeof(res));
+    res.proj.error = PGDTO_ERR_ARG;
     b->finish(r.ticket, PGDTO_ERR_ARG, res, r.footprint, now_ns(), now_ns());
     return true;
   }
   os_ticket = r.ticket;
   os_footprint = r.footprint;
   os_t_start = now_ns();
-  memset(os_res, 0, sizeof(pgdto_result));
-  int st = pgdto_project_async(os_ctx, &p, &r.params, os_res, (void*)os_stream);
+  memset(os_res, 0, sizeof(pgdto_pgd_out));
+  int st;
+  if (r.pgd) {
+    const pgdto_pgd_args a = r.pgd_args();
+    st = pgdto_pgd_step_async(os_ctx, &a, &r.params, os_res, (void*)os_stream);
+  } else {
+    st = pgdto_project_async(os_ctx, &p, &r.params, &os_res->proj, (void*)os_stream);
+  }
   if (st == PGDTO_OK && hipEventRecord(os_event, os_stream) != hipSuccess) st = PGDTO_ERR_HIP;
   if (st != PGDTO_OK) {
-    pgdto_result res;
+    pgdto_pgd_out res;
     memset(&res, 0, sizeof(res));
-    res.error = st;
+    res.proj.error = st;
     b->finish(r.ticket, st, res, r.footprint, os_t_start, now_ns());
     return true;
   }
@@ -194,8 +199,8 @@ bool Server::retire() {
     if (o.retired) continue;
     const uint64_t w = __atomic_load_n(&done[j % qcap], __ATOMIC_ACQUIRE);
     if (w != j + 1) continue;
-    const pgdto_result& r = results[j % qcap];
-    const int st = r.error != 0 ? r.error : PGDTO_OK;
+    const pgdto_pgd_out& r = results[j % qcap];
+    const int st = r.proj.error != 0 ? r.proj.error : PGDTO_OK;
     b->finish(o.ticket, st, r, o.footprint, o.t_start, now_ns());
     o.retired = true;
     any = true;
@@ -213,24 +218,23 @@ bool Server::admit() {
       std::lock_guard<std::mutex> lk(b->mu);
       if (!b->pop_admissible(r, 1)) break;
     }
-    pgdto_problem p = r.prob;
-    p.b = r.b;
-    p.block_offsets = r.prob.kind == PGDTO_INDEPENDENT ? r.off : nullptr;
     Desc d;
-    int st = build_desc(&p, &r.params, true, d);
-    if (st == PGDTO_OK && p.dtype != PGDTO_F32) st = PGDTO_ERR_ARG;
+    int st = build_request_desc(r, d);
+    if (st == PGDTO_OK && r.problem().dtype != PGDTO_F32) st = PGDTO_ERR_ARG;
     if (st != PGDTO_OK) {
-      pgdto_result res;
+      pgdto_pgd_out res;
       memset(&res, 0, sizeof(res));
+      res.proj.error = st;
       b->finish(r.ticket, st, res, r.footprint, now_ns(), now_ns());
       continue;
     }
     const uint64_t j = published;
     d.epoch0 = (j + 1) << 20;      // per slot barrier words: epochs grow with the job index
-    d.pgd = 0;
+    d.pgd = r.pgd;
     d.result = nullptr;
     d.trace = nullptr;
     jobs[j % qcap] = d;
+    memset(&results[j % qcap], 0, sizeof(pgdto_pgd_out));
     __atomic_store_n(&done[j % qcap], 0, __ATOMIC_RELAXED);
     out[j % qcap] = Out{r.ticket, r.footprint, now_ns(), false};
     published = j + 1;
@@ -249,9 +253,9 @@ void Server::fail_stranded() {
     Out& o = out[j % qcap];
     if (o.retired) continue;
     if (__atomic_load_n(&done[j % qcap], __ATOMIC_ACQUIRE) == j + 1) continue;
-    pgdto_result res;
+    pgdto_pgd_out res;
     memset(&res, 0, sizeof(res));
-    res.error = PGDTO_ERR_TIMEOUT;
+    res.proj.error = PGDTO_ERR_TIMEOUT;
     b->finish(o.ticket, PGDTO_ERR_TIMEOUT, res, o.footprint, o.t_start, now_ns());
     o.retired = true;
   }
@@ -312,9 +316,9 @@ void Server::loop() {
       for (uint64_t j = oldest; j < published; ++j) {
         Out& o = out[j % qcap];
         if (o.retired) continue;
-        pgdto_result res;
+        pgdto_pgd_out res;
         memset(&res, 0, sizeof(res));
-        res.error = PGDTO_ERR_HIP;
+        res.proj.error = PGDTO_ERR_HIP;
         b->finish(o.ticket, PGDTO_ERR_HIP, res, o.footprint, o.t_start, now_ns());
         o.retired = true;
       }

@@ -250,3 +250,62 @@ def test_server_rejects_f64(ctx, slots_only):
     st, r, _ = B.wait(t)
     B.close()
     assert st == N.ERR_ARG
+
+
+def pgd_states():
+    """Two single-row steps (t = 60 and t = 0) and one coupled step."""
+    out = [I.pgd_compliance_3d(2, t=60, n=70000), I.pgd_compliance_3d(3, t=0, n=33000)]
+    p = I.volume_com(1, grid=(96, 48), vf=0.3)
+    rng = np.random.default_rng(5)
+    n = p.n
+    rho = np.clip(rng.uniform(0, 1, n), I.LO, I.HI).astype(np.float32)
+    grad = rng.standard_normal(n).astype(np.float32)
+    rho_prev = (rho - 0.01 * rng.standard_normal(n)).astype(np.float32)
+    grad_prev = (grad + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    A = p.A.astype(np.float32)
+    g = A.astype(np.float64) @ rho.astype(np.float64)
+    prob = I.Problem("coupled", rho.copy(), A, p.b.copy(), C=p.C)
+    out.append(I.PgdState(rho, rho_prev, grad, grad_prev, (-grad_prev).astype(np.float32), prob, g, p.b.copy(), 60))
+    return out
+
+
+def stage_pgd(st):
+    from paper_2511_13905_amd.api import aligned_rows
+    A = dev(st.problem.A)
+    if A.dim() == 1:
+        A = A.reshape(1, -1)
+    return dict(A=aligned_rows(A), rho=dev(st.rho), rp=dev(st.rho_prev), gr=dev(st.grad), gp=dev(st.grad_prev),
+                d=dev(st.d_prev))
+
+
+@pytest.mark.parametrize("slots_only", [False, True])
+def test_served_pgd_steps_match_single_launch(ctx, slots_only):
+    """Algorithm 3 steps served (slots or the lone full-GPU route) give the
+    bits of pgdto_pgd_step: rho_{t+1}, d_t, alpha, beta, multipliers."""
+    from paper_2511_13905_amd.api import Batch
+    states = pgd_states()
+    say("served pgd steps", slots_only, [s.problem.n for s in states])
+    served = [stage_pgd(s) for s in states]
+    single_in = [stage_pgd(s) for s in states]
+    torch.cuda.synchronize()
+    B = Batch(ctx, max_slots=4, slots_only=slots_only)
+    tickets = []
+    for st, dv in zip(states, served):
+        t = B.submit_pgd(st.problem.kind, dv["A"], dv["rho"], dv["rp"] if st.t > 0 else None, dv["gr"],
+                         dv["gp"] if st.t > 0 else None, dv["d"], st.g, st.G, st.t, I.LO, I.HI, C=st.problem.C)
+        tickets.append(t)
+    xs = [B.x_of(t) for t in tickets]
+    outs = [B.poll_pgd(t, wait=True) for t in tickets]
+    B.close()
+    torch.cuda.synchronize()
+    for st, dv, dv1, x, (status, o, times) in zip(states, served, single_in, xs, outs):
+        assert status == 0, status
+        x1, o1 = ctx.pgd_step(st.problem.kind, dv1["A"], dv1["rho"], dv1["rp"] if st.t > 0 else None, dv1["gr"],
+                              dv1["gp"] if st.t > 0 else None, dv1["d"], st.g, st.G, st.t, I.LO, I.HI,
+                              C=st.problem.C)
+        torch.cuda.synchronize()
+        assert torch.equal(x, x1)
+        assert torch.equal(dv["d"], dv1["d"])
+        assert o["alpha"] == o1["alpha"] and o["beta"] == o1["beta"]
+        assert o["used_fallback"] == o1["used_fallback"] and o["rel_change"] == o1["rel_change"]
+        assert o["proj"]["lam"] == o1["proj"]["lam"] and o["proj"]["passes"] == o1["proj"]["passes"]
