@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream and batched measurements")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="grid autotuner of the one-instance launch (1: on, 0: off)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-pool", type=int, default=128,
                     help="distinct request instances the served stream cycles through")
@@ -147,6 +149,17 @@ def main():
             ctx.project_async(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, res_bufs[i % R], C=p.C,
                               offsets=p.offsets, x=it["x"])
 
+    if args.autotune:
+        # one blocking projection per shape class lets the context pick its grid
+        ctx.autotune(1)
+        it = insts[0]
+        if is_pgd:
+            st0 = it["st"]
+            ctx.project("single", it["rho"], it["A"], [float(st0.G[0] - st0.g[0]) + 0.0], I.LO, I.HI)
+        else:
+            p = it["p"]
+            ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C, offsets=p.offsets)
+        torch.cuda.synchronize()
     for i in range(args.warmup):
         launch(i)
     torch.cuda.synchronize()
@@ -208,7 +221,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "instances_rotated": R, "passes_per_launch": passes,
                    "latency_ms": {"p50": p50, "p99": p99}, "wall_s": wall, "device_errors": errors,
-                   "kernel_sha": kernel_sha()},
+                   "kernel_sha": kernel_sha(), "grid_workgroups": ctx.last_launch()[0],
+                   "tiles": ctx.last_launch()[1], "autotune": bool(args.autotune)},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic_for(wl),
                      "bytes_per_launch": bytes_launch, "kernel_ms": kern_ms},

@@ -194,6 +194,18 @@ void pgdto_pgd_args_default(pgdto_pgd_args* a);
 int pgdto_ctx_create(int device, pgdto_ctx** out);
 int pgdto_ctx_destroy(pgdto_ctx* ctx);
 
+/* Grid autotuner (also on when the environment variable PGDTO_AUTOTUNE is
+ * set at creation).  enable > 0: the first blocking pgdto_project of each
+ * shape class (kind, dtype, m, tile count) times the launch at all
+ * co-resident workgroups and at 1/2, 1/4, 1/8 of them on the caller's stream
+ * and keeps the fastest for the class (later calls of the class, async and
+ * pgd_step included, use it); 0: stop tuning, keep choices; < 0: stop and
+ * forget.  Results do not depend on the choice (bitwise).  Returns the
+ * previous setting or PGDTO_ERR_ARG. */
+int pgdto_ctx_autotune(pgdto_ctx* ctx, int enable);
+/* Workgroups and tiles of the context's last launch. */
+int pgdto_ctx_last_launch(pgdto_ctx* ctx, int32_t* grid, int32_t* tiles);
+
 /* Project (Alg. 1 / Alg. 2).  Enqueues one cooperative launch on `stream`
  * and waits for it; *out is filled on return.  params may be NULL. */
 int pgdto_project(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params,

@@ -97,6 +97,8 @@ SIGNATURES = {
     "pgdto_pgd_args_default": (None, [C.POINTER(PgdArgs)]),
     "pgdto_ctx_create": (C.c_int, [C.c_int, C.POINTER(_VP)]),
     "pgdto_ctx_destroy": (C.c_int, [_VP]),
+    "pgdto_ctx_autotune": (C.c_int, [_VP, C.c_int]),
+    "pgdto_ctx_last_launch": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pgdto_project": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), C.POINTER(Result), _VP]),
     "pgdto_project_async": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP]),
     "pgdto_pgd_step": (C.c_int, [_VP, C.POINTER(PgdArgs), C.POINTER(Params), C.POINTER(PgdOut), _VP]),

@@ -133,6 +133,16 @@ class Context:
         _check(N.lib().pgdto_ctx_create(device, C.byref(h)), "pgdto_ctx_create")
         self.h = h
 
+    def autotune(self, enable=1) -> int:
+        """pgdto_ctx_autotune: grid autotuning per shape class (returns the previous setting)."""
+        return N.lib().pgdto_ctx_autotune(self.h, int(enable))
+
+    def last_launch(self):
+        """(workgroups, tiles) of the last launch on this context."""
+        g, t = C.c_int32(), C.c_int32()
+        _check(N.lib().pgdto_ctx_last_launch(self.h, C.byref(g), C.byref(t)), "pgdto_ctx_last_launch")
+        return g.value, t.value
+
     def close(self):
         if getattr(self, "h", None):
             N.lib().pgdto_ctx_destroy(self.h)

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <unordered_map>
+
 #include "pgdto_internal.h"
 
 struct pgdto_ctx {
@@ -16,6 +18,10 @@ struct pgdto_ctx {
   int coop_cap[2][2][PGDTO_MAX_M + 1] = {};   // co-resident workgroups per kernel
   int last_grid = 0;
   int last_ntiles = 0;
+  // grid autotuner: workgroups chosen per (kind, dtype, m, tile count)
+  int autotune = 0;
+  std::unordered_map<uint64_t, int> tuned_grid;
+  int forced_grid = 0;                        // set while a candidate is timed
 };
 
 namespace pgdto {

@@ -110,6 +110,10 @@ extern "C" int pgdto_ctx_create(int device, pgdto_ctx** out) {
   ok = ok && hipMemset(c->sync, 0, SYNC_WORDS * sizeof(uint64_t)) == hipSuccess;
   ok = ok && hipMemset(c->part, 0, sizeof(double) * PART_DOUBLES) == hipSuccess;
   {
+    const char* av = getenv("PGDTO_AUTOTUNE");
+    c->autotune = (av && av[0] && av[0] != '0') ? 1 : 0;
+  }
+  {
     const char* tv = getenv("PGDTO_TRACE");
     if (tv && tv[0] && tv[0] != '0') {
       ok = ok && hipMalloc(&c->trace, sizeof(uint64_t) * TRACE_WORDS) == hipSuccess;
@@ -247,13 +251,27 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   return PGDTO_OK;
 }
 
-int grid_for(pgdto_ctx* c, const Desc& d) {
+static uint64_t tune_key(const Desc& d) {
+  return ((uint64_t)d.kind << 40) | ((uint64_t)d.dtype << 36) | ((uint64_t)d.m << 24) | (uint64_t)d.ntiles;
+}
+
+static int coresident_cap(pgdto_ctx* c, const Desc& d) {
   const int ki = d.kind == PGDTO_COUPLED ? 1 : 0;
   const int mi = d.kind == PGDTO_COUPLED ? d.m : 0;
   int& cap = c->coop_cap[ki][d.dtype][mi];
   if (cap == 0) cap = max_coresident(d.kind, d.dtype, d.m, c->device);
+  return cap;
+}
+
+// Workgroups of a one-instance launch: all that fit at once, capped by the
+// tile count; or the autotuner's choice for this shape class.
+int grid_for(pgdto_ctx* c, const Desc& d) {
+  const int cap = coresident_cap(c, d);
   if (cap <= 0) return 0;
-  return std::max(1, std::min(d.ntiles, cap));
+  const int full = std::max(1, std::min(d.ntiles, cap));
+  if (c->forced_grid > 0) return std::min(c->forced_grid, full);
+  auto it = c->tuned_grid.find(tune_key(d));
+  return it != c->tuned_grid.end() ? std::min(it->second, full) : full;
 }
 
 int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_pgd) {
@@ -347,9 +365,77 @@ extern "C" int pgdto_project_async(pgdto_ctx* c, const pgdto_problem* prob, cons
   return run_launch(c, d, (hipStream_t)stream, result_dev, false);
 }
 
+// Grid autotuner (pgdto_ctx_autotune): the first blocking projection of a
+// shape class (kind, dtype, m, tile count) is run once per candidate grid --
+// all co-resident workgroups, 1/2, 1/4, 1/8 of them -- timed with events on
+// the caller's stream, and the fastest is kept for the class.  Every run gives
+// the same bits (reductions follow the tiles, not the workgroups), so the
+// candidate runs leave exactly the result of a plain call.
+static int autotune_project(pgdto_ctx* c, const pgdto_problem* prob, const pgdto_params* params,
+                            hipStream_t s) {
+  pgdto_params tmp;
+  const pgdto_params* pp = params_or_default(params, tmp);
+  Desc d;
+  int st = build_desc(prob, pp, true, d);
+  if (st != PGDTO_OK) return st;
+  const uint64_t key = tune_key(d);
+  if (c->tuned_grid.count(key)) return PGDTO_OK;
+  const int cap = coresident_cap(c, d);
+  if (cap <= 0) return PGDTO_ERR_HIP;
+  const int full = std::max(1, std::min(d.ntiles, cap));
+  int cand[4], nc = 0;
+  for (int div = 1; div <= 8; div *= 2) {
+    const int g = std::max(1, full / div);
+    if (nc == 0 || cand[nc - 1] != g) cand[nc++] = g;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return PGDTO_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return PGDTO_ERR_HIP; }
+  int best = full;
+  float best_ms = 1e30f;
+  st = PGDTO_OK;
+  for (int rep = 0; rep < 2 && st == PGDTO_OK; ++rep) {   // the first round warms up
+    for (int i = 0; i < nc && st == PGDTO_OK; ++i) {
+      c->forced_grid = cand[i];
+      if (hipEventRecord(e0, s) != hipSuccess) { st = PGDTO_ERR_HIP; break; }
+      st = pgdto_project_async(c, prob, params, (pgdto_result*)c->res_dev, s);
+      if (st != PGDTO_OK) break;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = PGDTO_ERR_HIP; break; }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = PGDTO_ERR_HIP; break; }
+      if (rep == 1 && ms < best_ms) { best_ms = ms; best = cand[i]; }
+    }
+  }
+  c->forced_grid = 0;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == PGDTO_OK) c->tuned_grid[key] = best;
+  return st;
+}
+
+extern "C" int pgdto_ctx_autotune(pgdto_ctx* c, int enable) {
+  if (!c) return PGDTO_ERR_ARG;
+  const int prev = c->autotune;
+  c->autotune = enable ? 1 : 0;
+  if (enable < 0) c->tuned_grid.clear();
+  return prev;
+}
+
+extern "C" int pgdto_ctx_last_launch(pgdto_ctx* c, int32_t* grid, int32_t* tiles) {
+  if (!c || !grid || !tiles) return PGDTO_ERR_ARG;
+  *grid = c->last_grid;
+  *tiles = c->last_ntiles;
+  return PGDTO_OK;
+}
+
 extern "C" int pgdto_project(pgdto_ctx* c, const pgdto_problem* prob, const pgdto_params* params,
                              pgdto_result* out, void* stream) {
   if (!c || !prob || !out) return PGDTO_ERR_ARG;
+  if (c->autotune) {
+    if (hipSetDevice(c->device) != hipSuccess) return PGDTO_ERR_HIP;
+    const int ts = autotune_project(c, prob, params, (hipStream_t)stream);
+    if (ts != PGDTO_OK) return ts;
+  }
   int st = pgdto_project_async(c, prob, params, (pgdto_result*)c->res_dev, stream);
   if (st != PGDTO_OK) return st;
   st = finish_blocking(c, (hipStream_t)stream, sizeof(pgdto_result), out);
