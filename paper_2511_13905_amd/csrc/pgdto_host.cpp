@@ -235,7 +235,7 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   // tiles: size depends only on n and dtype
   // 1-D kernel: two workgroups per CU (512 tiles); coupled: one (256 tiles)
   const int64_t unit = tile_unit(pr->dtype);
-  const int64_t target = pr->kind == PGDTO_COUPLED ? TARGET_TILES / 2 : TARGET_TILES;
+  const int64_t target = TARGET_TILES / 2;
   int64_t tile = (n + target - 1) / target;
   tile = std::max<int64_t>(unit, (tile + unit - 1) / unit * unit);
   d.tile_elems = tile;

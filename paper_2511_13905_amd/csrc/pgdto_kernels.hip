@@ -770,7 +770,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   // Register residency: the first tile of this workgroup keeps its y (pgd:
   // rho~) and a slots in registers across passes when it has at most RS
   // vector slots per thread; later passes then read no memory for it.
-  constexpr int RS = 4;
+  constexpr int RS = 8;
   T ry[RS][V], ra[RS][V];
   bool resident = false;
   uint32_t rbits = 0u;      // element-validity masks of the resident slots, V bits each
@@ -1179,7 +1179,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK, 4) void k_solve_1d(const Desc) {
+__global__ __launch_bounds__(BLOCK, 2) void k_solve_1d(const Desc) {
   __shared__ Sh1D sh;
   __shared__ Desc sd;
   load_desc(sd);
