@@ -112,6 +112,10 @@ extern "C" int pgdto_ctx_create(int device, pgdto_ctx** out) {
   {
     const char* av = getenv("PGDTO_AUTOTUNE");
     c->autotune = (av && av[0] && av[0] != '0') ? 1 : 0;
+    // PGDTO_GRID=k: one-instance launches use at most k workgroups (the
+    // size of a server slot, to study a slot's passes in isolation)
+    const char* gv = getenv("PGDTO_GRID");
+    if (gv && gv[0]) c->forced_grid = std::max(0, atoi(gv));
   }
   {
     const char* tv = getenv("PGDTO_TRACE");
@@ -393,6 +397,7 @@ static int autotune_project(pgdto_ctx* c, const pgdto_problem* prob, const pgdto
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return PGDTO_ERR_HIP; }
   int best = full;
   float best_ms = 1e30f;
+  const int saved_grid = c->forced_grid;
   st = PGDTO_OK;
   for (int rep = 0; rep < 2 && st == PGDTO_OK; ++rep) {   // the first round warms up
     for (int i = 0; i < nc && st == PGDTO_OK; ++i) {
@@ -406,7 +411,7 @@ static int autotune_project(pgdto_ctx* c, const pgdto_problem* prob, const pgdto
       if (rep == 1 && ms < best_ms) { best_ms = ms; best = cand[i]; }
     }
   }
-  c->forced_grid = 0;
+  c->forced_grid = saved_grid;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st == PGDTO_OK) c->tuned_grid[key] = best;

@@ -72,17 +72,26 @@ __device__ __forceinline__ void ld_vec_whole(const __attribute__((address_space(
   }
 }
 
-// One vector slot: V elements from e0 (elements at or past n read as 0).
+// One vector slot near the array's end: V element loads from e0, each
+// address clamped into [0, n) (n >= 1 on every launch) and elements at or
+// past n replaced by 0.  Every lane issues exactly V loads with no branch, so
+// the compiler can count the loads in flight and wait only for older ones.
+template <typename T>
+__device__ __forceinline__ void ld_vec_tail(const __attribute__((address_space(1))) T* p, int64_t e0, int64_t n, T* o) {
+  constexpr int V = VT<T>::N;
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const T v = p[min(e0 + k, n - 1)];
+    o[k] = (e0 + k < n) ? v : (T)0;
+  }
+}
+
+// One vector slot, the whole-vector or the tail form chosen per lane.
 template <typename T>
 __device__ __forceinline__ void ld_vec(const T* __restrict__ p0, int64_t e0, int64_t n, bool, T* o) {
-  constexpr int V = VT<T>::N;
   const auto p = gptr(p0);
-  if (e0 + V <= n) {
-    ld_vec_whole<T>(p, e0, o);
-  } else {
-#pragma unroll
-    for (int k = 0; k < V; ++k) o[k] = (e0 + k < n) ? p[e0 + k] : (T)0;
-  }
+  if (e0 + VT<T>::N <= n) ld_vec_whole<T>(p, e0, o);
+  else ld_vec_tail<T>(p, e0, n, o);
 }
 
 // K vector slots of NS streams at once.  When every lane of the wave has all
@@ -107,7 +116,7 @@ __device__ __forceinline__ void ld_slots(const T* const* ptrs, const int64_t* e0
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int q = 0; q < NS; ++q) ld_vec<T>(ptrs[q], e0[k], n, false, buf[k][q]);
+      for (int q = 0; q < NS; ++q) ld_vec_tail<T>(gptr(ptrs[q]), e0[k], n, buf[k][q]);
   }
 }
 
@@ -136,6 +145,19 @@ template <typename T>
 __device__ __forceinline__ double f64(T v) { return (double)v; }
 
 __device__ __forceinline__ double clampd(double z, double lo, double hi) { return fmin(fmax(z, lo), hi); }
+
+// Breakpoint of one element, (y - bound)/a with a != 0: the multiplier at
+// which the element reaches its bound (Appendix A.1).  The reciprocal of a is
+// refined by two Newton steps, so the quotient is within a few ulps of the
+// correctly rounded one at a third of the cost of a full division.  Only the
+// largest breakpoint is used, as the end of the search bracket (the smallest
+// multiplier at which every element is saturated).
+__device__ __forceinline__ double breakpoint(double y, double av, double bound) {
+  double r = __builtin_amdgcn_rcp(av);
+  r = fma(r, fma(-av, r, 1.0), r);
+  r = fma(r, fma(-av, r, 1.0), r);
+  return (y - bound) * r;
+}
 
 // ------------------------------------------------------------------ reductions
 
@@ -817,9 +839,9 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           acc[0] = fma(av, x0, acc[0]);
           if (y >= lo && y <= hi) acc[1] = fma(av, av, acc[1]);
           if (av != 0.0) {
-            const double bp = (av > 0.0) ? (y - lo) / av : (y - hi) / av;
-            acc[2] = fmax(acc[2], bp);
-            acc[3] += (av > 0.0) ? av * lo : av * hi;
+            const double bound = (av > 0.0) ? lo : hi;
+            acc[2] = fmax(acc[2], breakpoint(y, av, bound));
+            acc[3] = fma(av, bound, acc[3]);
           }
           acc[4] += fabs(av);
           if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
@@ -952,42 +974,51 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       } else if (ph == PH_SEARCH) {
         nv = 2 * NT; maxmask = 0;
         if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
-        double acc[2 * NT] = {0, 0, 0, 0};
         const double l0 = sh.S.trial[s][0], l1 = sh.S.trial[s][1];
         // phi(lam_t) + b = a.clip(y - lam_t a) and its slope sum_free a^2, per trial;
-        // elements outside the segment enter with a = 0, y = 0 and add nothing
+        // elements outside the segment enter with a = 0, y = 0 and add nothing.
+        // Two chains per sum (even and odd element of a vector), added at the
+        // end of the tile.  The slope only steers the choice of trial points,
+        // so with float streams it is summed in float (a^2 exact in float
+        // up to rounding; a thread adds at most 32 terms per tile).
+        using S = typename std::conditional<sizeof(T) == 4, float, double>::type;
+        double cs[2][2] = {{0, 0}, {0, 0}};     // [chain][trial]
+        S sl[2][2] = {{0, 0}, {0, 0}};
         auto run = [&](auto two_c) __attribute__((always_inline)) {
           constexpr bool TWO = decltype(two_c)::value;
-          auto elem = [&](double yq, double av) __attribute__((always_inline)) {
-            const double a2 = av * av;
+          auto elem = [&](T yt, T at, int c) __attribute__((always_inline)) {
+            const double yq = f64(yt), av = f64(at);
+            const S a2 = (S)at * (S)at;
             const double z0 = fma(-l0, av, yq);
             const double x0 = fmin(fmax(z0, lo), hi);
-            acc[0] = fma(av, x0, acc[0]);
-            acc[1] += (x0 == z0) ? a2 : 0.0;          // free: the clip left z unchanged
+            cs[c][0] = fma(av, x0, cs[c][0]);
+            sl[c][0] += (x0 == z0) ? a2 : (S)0;     // free: the clip left z unchanged
             if constexpr (TWO) {
               const double z1 = fma(-l1, av, yq);
               const double x1 = fmin(fmax(z1, lo), hi);
-              acc[2] = fma(av, x1, acc[2]);
-              acc[3] += (x1 == z1) ? a2 : 0.0;
+              cs[c][1] = fma(av, x1, cs[c][1]);
+              sl[c][1] += (x1 == z1) ? a2 : (S)0;
             }
           };
           if (tile == wid && resident) {
 #pragma unroll
             for (int k = 0; k < RS; ++k)
 #pragma unroll
-              for (int q = 0; q < V; ++q) elem(f64(ry[k][q]), f64(ra[k][q]));
+              for (int q = 0; q < V; ++q) elem(ry[k][q], ra[k][q], q & 1);
           } else {
             const T* ptr[2] = {Y, A};
             stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
               for (int q = 0; q < V; ++q) {
                 const bool ok = (mask >> q) & 1u;
-                elem(ok ? f64(b[0][q]) : 0.0, ok ? f64(b[1][q]) : 0.0);
+                elem(ok ? b[0][q] : (T)0, ok ? b[1][q] : (T)0, q & 1);
               }
             });
           }
         };
         if (l1 == l1) run(std::true_type{}); else run(std::false_type{});
+        const double acc[2 * NT] = {cs[0][0] + cs[1][0], (double)sl[0][0] + (double)sl[1][0],
+                                    cs[0][1] + cs[1][1], (double)sl[0][1] + (double)sl[1][1]};
         block_to_part<2 * NT>(acc, nv, maxmask, sh.red, pb, tile);
       } else {  // PH_FINAL
         nv = 4; maxmask = 0;
@@ -1589,9 +1620,9 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
               acc[j] = fma(av, x0, acc[j]);
               if (fr) acc[M + j] = fma(av, av, acc[M + j]);
               if (av != 0.0) {
-                const double bp = (av > 0.0) ? (y - lo) / av : (y - hi) / av;
-                acc[2 * M + j] = fmax(acc[2 * M + j], bp);
-                acc[3 * M + j] += (av > 0.0) ? av * lo : av * hi;
+                const double bound = (av > 0.0) ? lo : hi;
+                acc[2 * M + j] = fmax(acc[2 * M + j], breakpoint(y, av, bound));
+                acc[3 * M + j] = fma(av, bound, acc[3 * M + j]);
               }
               acc[4 * M + j] += fabs(av);
               bad |= !isfinite(av);
