@@ -243,14 +243,14 @@ def _pctl(v, q):
     return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
 
 
-def _run_stream(ctx, structs, params, max_slots, arrivals):
+def _run_stream(ctx, structs, params, max_slots, arrivals, wg_per_slot=0):
     """Submit the pre-built requests at the given arrival offsets (s) through
     one pgdto_batch; returns per-request (submit, admit, done) ns and statuses."""
     import ctypes as C
     from paper_2511_13905_amd import _native as N
     from paper_2511_13905_amd.api import Batch
     L = N.lib()
-    B = Batch(ctx, max_slots=max_slots)
+    B = Batch(ctx, max_slots=max_slots, wg_per_slot=wg_per_slot)
     tickets = []
     t0 = time.perf_counter()
     for st, at in zip(structs, arrivals):
@@ -341,18 +341,21 @@ def serve_bench(ctx, args):
 
 
 def batched_bench(ctx):
-    """32 projections of the 256x128x128 single-row problem (8 distinct
+    """64 projections of the 256x128x128 single-row problem (8 distinct
     instances, distinct outputs) through the persistent executor, all
-    submitted at once: algorithmic bytes of every pass over wall time."""
-    import numpy as np
+    submitted at once: algorithmic bytes of every pass over wall time.  The
+    executor shape (slots x workgroups per slot) comes from
+    pgdto_batch_autotune on the same instances; the default serving shape is
+    measured beside it."""
     import torch
     from paper_2511_13905_amd import inputs as I
-    from paper_2511_13905_amd.api import make_params, problem_struct, _Keep
+    from paper_2511_13905_amd.api import make_params, problem_struct, _Keep, batch_autotune
     pool = [I.compliance_3d(s) for s in range(8)]
     dev = [(torch.from_numpy(p.y).to("cuda:0"), torch.from_numpy(p.A).to("cuda:0")) for p in pool]
+    nreq = 64
     keep = _Keep()
     structs, xs = [], []
-    for i in range(32):
+    for i in range(nreq):
         p = pool[i % 8]
         y, A = dev[i % 8]
         x = torch.empty(p.n, dtype=torch.float32, device="cuda:0")
@@ -361,23 +364,44 @@ def batched_bench(ctx):
         xs.append(x)
     torch.cuda.synchronize()
     params = make_params()
-    _run_stream(ctx, structs[:8], params, 0, [0.0] * 8)      # warm-up
-    times, status, shape = _run_stream(ctx, structs, params, 0, [0.0] * 32)
-    wall = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
+    tune_x = [torch.empty(p.n, dtype=torch.float32, device="cuda:0") for p in pool]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    (slots, wg), cand_ms = batch_autotune(
+        ctx, [(p.kind, y, A, p.b, p.lo, p.hi, p.C, None, x) for p, (y, A), x in zip(pool, dev, tune_x)],
+        count=nreq, params=params)
+    tune_s = time.perf_counter() - t0
     n = pool[0].n
-    # passes: from one single-launch run per instance (same bits and pass count)
-    from paper_2511_13905_amd.api import Context
     passes = []
     for p, (y, A) in zip(pool, dev):
         _, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C)
         passes.append(r["passes"])
-    per = [passes[i % 8] for i in range(32)]
+    per = [passes[i % 8] for i in range(nreq)]
     alg = sum(pp * n * 8 + n * 4 for pp in per)
-    return {"workload": "32 x project, single compliance row, 256x128x128 (n=4194304), float32, 8 distinct inputs",
-            "errors": sum(1 for x in status if x != 0), "wall_s": wall, "projections_per_s": 32 / wall,
-            "elements_per_s": 32 * n / wall, "passes_mean": sum(per) / 32,
-            "algorithmic_GBps": alg / wall / 1e9, "hbm_frac": alg / wall / HBM_PEAK,
-            "server_shape": {"slots": shape[0], "wg_per_slot": shape[1]}}
+
+    def measure(max_slots, wg_per_slot):
+        _run_stream(ctx, structs[:16], params, max_slots, [0.0] * 16, wg_per_slot)     # warm-up
+        best = None
+        for _ in range(3):
+            times, status, shape = _run_stream(ctx, structs, params, max_slots, [0.0] * nreq, wg_per_slot)
+            wall = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
+            if best is None or wall < best[0]:
+                best = (wall, status, shape)
+        wall, status, shape = best
+        return {"errors": sum(1 for x in status if x != 0), "wall_s": wall, "projections_per_s": nreq / wall,
+                "elements_per_s": nreq * n / wall, "algorithmic_GBps": alg / wall / 1e9,
+                "hbm_frac": alg / wall / HBM_PEAK, "server_shape": {"slots": shape[0], "wg_per_slot": shape[1]}}
+
+    tuned = measure(slots, wg)
+    default = measure(0, 0)
+    out = {"workload": f"{nreq} x project, single compliance row, 256x128x128 (n=4194304), float32, "
+                       "8 distinct inputs, all submitted at once",
+           "passes_mean": sum(per) / nreq,
+           "autotune": {"candidates_slots": [4, 8, 16, 32], "wall_ms": cand_ms, "chosen": [slots, wg],
+                        "tuning_s": tune_s},
+           "default_shape": default}
+    out.update(tuned)
+    return out
 
 
 def cpu_baseline(wl, insts, budget_s, n):

@@ -279,6 +279,24 @@ int pgdto_batch_poll_timed(pgdto_batch* b, uint64_t ticket, pgdto_result* out, i
 int pgdto_batch_poll_pgd(pgdto_batch* b, uint64_t ticket, pgdto_pgd_out* out, int64_t* times, int wait);
 /* Executor shape: slots and workgroups per slot (0, 0 on the plain path). */
 int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot);
+/* Shape autotuner for the persistent executor (blocks per instance).  Runs
+ * `count` float32 requests, taken round-robin from samples[0..nsamples-1]
+ * (distinct instances, so that inputs are not all served from cache), all
+ * submitted at once, through executors of PGDTO_TUNE_SHAPES candidate
+ * shapes: 4, 8, 16, 32 slots, each with the co-resident workgroups split
+ * evenly; every shape runs twice and its faster run counts.  Writes the
+ * fastest shape to *slots, *wg_per_slot (for pgdto_batch_cfg.max_slots and
+ * wg_per_slot) and, when times_ms is not NULL, the wall time of each
+ * candidate (first submit to last completion, ms; INFINITY for a shape the
+ * device cannot hold) to times_ms[0..PGDTO_TUNE_SHAPES-1].  Blocking.  The
+ * samples follow the pgdto_batch_submit contract for their buffers; their x
+ * is written (by several requests at once, with the same values) and their
+ * free_mask is ignored.  PGDTO_ERR_ARG for a bad argument or a float64
+ * sample; otherwise the first error of a request. */
+#define PGDTO_TUNE_SHAPES 4
+int pgdto_batch_autotune(pgdto_ctx* ctx, const pgdto_problem* samples, int nsamples,
+                         const pgdto_params* params, int count, int32_t* slots, int32_t* wg_per_slot,
+                         float* times_ms);
 /* Statistics: admitted, completed, queued, in flight, peak footprint. */
 int pgdto_batch_stats(pgdto_batch* b, int64_t* admitted, int64_t* completed, int64_t* queued,
                       int64_t* in_flight, int64_t* peak_bytes);

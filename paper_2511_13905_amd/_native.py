@@ -112,6 +112,8 @@ SIGNATURES = {
     "pgdto_batch_poll_pgd": (C.c_int, [_VP, C.c_uint64, C.POINTER(PgdOut), C.POINTER(C.c_int64), C.c_int]),
     "pgdto_batch_shape": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pgdto_batch_stats": (C.c_int, [_VP] + [C.POINTER(C.c_int64)] * 5),
+    "pgdto_batch_autotune": (C.c_int, [_VP, C.POINTER(Problem), C.c_int, C.POINTER(Params), C.c_int,
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "pgdto_batch_destroy": (C.c_int, [_VP]),
     "pgdto_status_string": (C.c_char_p, [C.c_int]),
     "pgdto_version": (C.c_int, []),

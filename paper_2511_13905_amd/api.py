@@ -336,5 +336,27 @@ class Batch:
             pass
 
 
+TUNE_SHAPES = 4
+
+
+def batch_autotune(ctx: Context, problems, count: int = 64, params=None):
+    """pgdto_batch_autotune: the executor shape (slots, workgroups per slot)
+    with the highest throughput on `count` requests drawn round-robin from
+    `problems` (a list of (kind, y, A, b, lo, hi, C, offsets, x) tuples whose
+    tensors are ready), plus the wall time in ms of every candidate shape."""
+    keep = _Keep()
+    arr = (N.Problem * len(problems))()
+    for i, (kind, y, A, b, lo, hi, C_pen, offsets, x) in enumerate(problems):
+        st, _, _ = problem_struct(kind, y, A, b, lo, hi, C_pen, offsets, x, None, keep, copy_ok=False)
+        arr[i] = st
+    s, w = C.c_int32(), C.c_int32()
+    times = (C.c_float * TUNE_SHAPES)()
+    pp = params if params is not None else make_params()
+    _check(N.lib().pgdto_batch_autotune(ctx.h, arr, len(problems), C.byref(pp), int(count), C.byref(s),
+                                        C.byref(w), times), "pgdto_batch_autotune")
+    del keep
+    return (s.value, w.value), [float(t) for t in times]
+
+
 def C_u64():
     return C.c_uint64()

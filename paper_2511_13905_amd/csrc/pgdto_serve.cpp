@@ -11,6 +11,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -205,6 +206,65 @@ extern "C" int pgdto_batch_destroy(pgdto_batch* b) {
   if (!b) return PGDTO_ERR_ARG;
   b->stop();
   delete b;
+  return PGDTO_OK;
+}
+
+// ------------------------------------------------------------------ shape autotuner
+
+// Times the persistent executor at each candidate shape (slots x workgroups
+// per slot, all co-resident workgroups split evenly) on `count` requests
+// drawn round-robin from the samples, all submitted at once, twice per shape
+// (the faster run counts), and reports the shape with the shortest wall time
+// from the first submit to the last completion.
+extern "C" int pgdto_batch_autotune(pgdto_ctx* ctx, const pgdto_problem* samples, int nsamples,
+                                    const pgdto_params* params, int count, int32_t* slots,
+                                    int32_t* wg_per_slot, float* times_ms) {
+  if (!ctx || !samples || nsamples < 1 || count < 1 || !slots || !wg_per_slot) return PGDTO_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PGDTO_ERR_HIP;
+  const int cap = server_coresident(ctx->device);
+  if (cap <= 0) return PGDTO_ERR_HIP;
+  std::vector<pgdto_problem> reqs(nsamples);
+  for (int i = 0; i < nsamples; ++i) {
+    reqs[i] = samples[i];
+    reqs[i].free_mask = nullptr;   // copies of one sample write identical x, and no mask
+    if (reqs[i].dtype != PGDTO_F32) return PGDTO_ERR_ARG;
+  }
+  int best_s = 0, best_w = 0;
+  float best_ms = INFINITY;
+  for (int c = 0; c < PGDTO_TUNE_SHAPES; ++c) {
+    const int s = 4 << c;
+    const int w = cap / s;
+    float shape_ms = INFINITY;
+    if (w >= 1 && w <= GMAX) {
+      for (int rep = 0; rep < 2; ++rep) {
+        pgdto_batch_cfg cfg{};
+        cfg.max_slots = s;
+        cfg.wg_per_slot = w;
+        cfg.slots_only = 1;
+        pgdto_batch* b = nullptr;
+        int st = pgdto_batch_create(ctx, &cfg, &b);
+        if (st != PGDTO_OK) return st;
+        std::vector<uint64_t> tk(count);
+        const int64_t t0 = clock_ns();
+        for (int i = 0; i < count && st == PGDTO_OK; ++i) st = pgdto_batch_submit(b, &reqs[i % nsamples], params, &tk[i]);
+        int64_t t1 = t0;
+        for (int i = 0; i < count && st == PGDTO_OK; ++i) {
+          pgdto_result r;
+          int64_t tm[3];
+          st = pgdto_batch_poll_timed(b, tk[i], &r, tm, 1);
+          t1 = std::max(t1, tm[2]);
+        }
+        (void)pgdto_batch_destroy(b);
+        if (st != PGDTO_OK) return st;
+        shape_ms = std::min(shape_ms, (float)((t1 - t0) * 1e-6));
+      }
+      if (shape_ms < best_ms) { best_ms = shape_ms; best_s = s; best_w = w; }
+    }
+    if (times_ms) times_ms[c] = shape_ms;
+  }
+  if (best_s == 0) return PGDTO_ERR_HIP;
+  *slots = best_s;
+  *wg_per_slot = best_w;
   return PGDTO_OK;
 }
 

@@ -98,6 +98,29 @@ def test_server_shape(ctx):
     B.close()
 
 
+def test_batch_autotune_picks_fastest_shape(ctx):
+    from paper_2511_13905_amd.api import Batch, aligned_rows, batch_autotune
+    reqs = [I.compliance_3d(s, n=200003) for s in range(4)]
+    say("batch autotune", [p.n for p in reqs])
+    probs, xs = [], []
+    for p in reqs:
+        x = torch.full((p.n,), -1.0, dtype=torch.float32, device="cuda:0")
+        probs.append((p.kind, dev(p.y), aligned_rows(dev(p.A)), p.b, p.lo, p.hi, p.C, p.offsets, x))
+        xs.append(x)
+    torch.cuda.synchronize()
+    (s, w), times = batch_autotune(ctx, probs, count=16)
+    cand = [4, 8, 16, 32]
+    assert len(times) == len(cand) and all(np.isfinite(t) and t > 0 for t in times), times
+    assert s in cand and times[cand.index(s)] == min(times)
+    B = Batch(ctx, max_slots=s, wg_per_slot=w, slots_only=True)
+    assert B.shape() == (s, w)
+    B.close()
+    # every request the tuner ran wrote the same bits as a single launch
+    for p, x in zip(reqs, xs):
+        xs_, _, _ = single(ctx, p)
+        assert np.array_equal(x.cpu().numpy(), xs_)
+
+
 @pytest.mark.parametrize("slots", [2, 8])
 def test_server_matches_single_launch_bitwise(ctx, slots):
     from paper_2511_13905_amd.api import Batch
