@@ -293,7 +293,9 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   if (d.free_mask) {
     if (hipMemsetAsync(d.free_mask, 0, (size_t)((d.n + 31) / 32) * 4, s) != hipSuccess) return PGDTO_ERR_HIP;
   }
-  hipError_t e = launch_solve(d, grid, s, true);
+  // an ordinary launch: the kernel's arrival door admits the workgroups that
+  // are running together (normally all of them) and sends late ones home
+  hipError_t e = launch_solve(d, grid, s, false);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     (void)launch_mark_error(result_dev, is_pgd ? 1 : 0, s);

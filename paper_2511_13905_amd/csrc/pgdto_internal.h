@@ -20,7 +20,9 @@ constexpr int GMAX = 1024;                 // workgroups of one launch (upper bo
 constexpr int TOT_MAX = 1024;              // per-segment totals of one pass
 constexpr int NREP = 64;                   // copies of the go word, each with the totals beside it
 constexpr int REP_WORDS = 128;             // 1 KiB per copy: go word + up to 127 totals
-constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + (size_t)NREP * REP_WORDS + 16 + TOT_MAX;   // uint64 words
+// flags, go-word replicas, error line, totals, then two lines for the arrival
+// door of one-instance launches
+constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + (size_t)NREP * REP_WORDS + 16 + TOT_MAX + 32;   // uint64 words
 
 // Bounded spin of the grid barrier: about a second of waiting before the
 // workgroup gives up, flags PGDTO_ERR_TIMEOUT and leaves the kernel.

@@ -1209,11 +1209,81 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   report_error(d, errp);
 }
 
+// ------------------------------------------------------------------ arrival door
+// One-instance launches are ordinary launches (a cooperative launch costs the
+// runtime about 17 us more per launch), so that all of the grid is resident
+// is not guaranteed; the grid barrier needs every participant running.  Each
+// workgroup therefore takes a ticket at entry with one atomic add on the
+// launch's door word.  The first arrival waits (bounded) until the whole grid
+// has arrived, closes the door and publishes the count; a workgroup arriving
+// after that leaves at once, and the participants take their ticket as
+// workgroup id.  Results do not depend on the count (tile-ordered
+// reductions).  The door word carries the launch's tag (from epoch0, unique
+// per launch of a context) in its upper half, so no reset between launches is
+// needed: the first arrivals of a launch replace a stale word.
+constexpr uint64_t DOOR_CLOSED = 1ull << 31;
+constexpr uint64_t DOOR_COUNT = DOOR_CLOSED - 1;
+constexpr uint64_t DOOR_WAIT_TICKS = 3000;     // 30 us on the 100 MHz clock
+
+__device__ __forceinline__ uint64_t* door_words(const Desc& d) {
+  return d.sync + (size_t)GMAX * FLAG_STRIDE + (size_t)NREP * REP_WORDS + FLAG_STRIDE + TOT_MAX;
+}
+
+// false: this workgroup arrived after the door closed and must leave.
+__device__ __forceinline__ bool enter_launch(Desc& sd, int32_t* late_sh) {
+  if (threadIdx.x == 0) {
+    uint64_t* door = door_words(sd);
+    uint64_t* pub = door + FLAG_STRIDE;
+    const uint64_t tag = (sd.epoch0 >> 20) & 0xffffffffull;
+    uint64_t cur = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // a stale word changes only when a workgroup of this launch opens it:
+    // at most two rounds
+    while ((cur >> 32) != tag) {
+      if (__hip_atomic_compare_exchange_strong(door, &cur, tag << 32, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT))
+        break;
+    }
+    const uint64_t old = __hip_atomic_fetch_add(door, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int late = (old & DOOR_CLOSED) != 0;
+    const int ticket = (int)(old & DOOR_COUNT);
+    int count = 0;
+    if (!late && ticket == 0) {
+      const uint64_t t0 = clk();
+      while ((__hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DOOR_COUNT) < gridDim.x &&
+             clk() - t0 < DOOR_WAIT_TICKS)
+        __builtin_amdgcn_s_sleep(1);
+      const uint64_t fin = __hip_atomic_fetch_or(door, DOOR_CLOSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      count = (int)(fin & DOOR_COUNT);
+      __hip_atomic_store(pub, (tag << 32) | (uint64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (!late) {
+      // the first arrival is running and publishes within the wait above;
+      // the spin cap only guards against the impossible
+      uint64_t v = 0;
+      uint32_t spins = 0;
+      while (((v = __hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT) break;
+      }
+      if ((v >> 32) == tag) count = (int)(v & 0xffffffffull);
+      else late = 1;
+    }
+    if (!late) {
+      sd.wg_base = (int32_t)blockIdx.x - ticket;
+      sd.wg_count = count;
+    }
+    *late_sh = late;
+  }
+  __syncthreads();
+  return *late_sh == 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK, 2) void k_solve_1d(const Desc) {
   __shared__ Sh1D sh;
   __shared__ Desc sd;
+  __shared__ int32_t late;
   load_desc(sd);
+  if (!enter_launch(sd, &late)) return;
   solve_1d<T>(sh, sd);
 }
 
@@ -2002,7 +2072,9 @@ template <typename T, int M>
 __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
   __shared__ ShC sh;
   __shared__ Desc sd;
+  __shared__ int32_t late;
   load_desc(sd);
+  if (!enter_launch(sd, &late)) return;
   solve_coupled<T, M>(sh, sd);
 }
 
