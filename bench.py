@@ -53,8 +53,11 @@ def parse():
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
 MEASURED_TRAFFIC = {
     # profiles/k_solve_1d_f32_pgd_compliance_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "2633e7d790b0806e", "bytes_per_launch": 278090623,
-                       "read": 191416134, "written": 86674490},
+    "pgd_compliance": {"kernel_sha": "d1b628a4a1092e84", "bytes_per_launch": 214123440,
+                       "read": 180229816, "written": 33893624},
+    # profiles/k_solve_1d_f32_project_compliance_hbm_traffic.md
+    "project_compliance": {"kernel_sha": "d1b628a4a1092e84", "bytes_per_launch": 52116200,
+                           "read": 35098068, "written": 17018132},
 }
 
 
