@@ -236,8 +236,8 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
     d.off[0] = 0;
     d.off[1] = n;
   }
-  // tiles: size depends only on n and dtype
-  // 1-D kernel: two workgroups per CU (512 tiles); coupled: one (256 tiles)
+  // tiles: size depends only on n and dtype; about n/256 elements (one tile
+  // per workgroup of a full-GPU launch, one 512-thread workgroup per CU)
   const int64_t unit = tile_unit(pr->dtype);
   const int64_t target = TARGET_TILES / 2;
   int64_t tile = (n + target - 1) / target;

@@ -11,7 +11,7 @@ namespace pgdto {
 constexpr int BLOCK = 512;                 // threads per workgroup (8 wave64)
 constexpr int NWAVE = BLOCK / 64;
 constexpr int NT = 2;                      // trial multipliers per 1-D search pass
-constexpr int TARGET_TILES = 512;          // tiles per instance (tile size follows n)
+constexpr int TARGET_TILES = 512;          // bound the partial-sum layout is sized for (instances use half)
 constexpr int MAX_TILES = TARGET_TILES + PGDTO_MAX_BLOCKS + 8;
 constexpr int TILES_PAD = 704;             // stride of the partial-sum table
 constexpr int VMAX = 112;                  // partial values per tile (coupled, m = 8)
