@@ -113,7 +113,13 @@ typedef struct {
                                    0 = o_0 < o_1 < ... < o_m = n               */
   const double* b;              /* host [m]: right-hand sides of A x <= b       */
   double lo, hi;                /* box, finite, lo < hi                         */
-  double C;                     /* penalty; kappa = 2/C; INFINITY: kappa = 0   */
+  double C;                     /* penalty; kappa = 2/C; INFINITY: kappa = 0.
+                                   C < 0: automatic, C = 2 max_j bp_j / tau with
+                                   tau = -C (the bound on constraint violation
+                                   of the regularized projection, Appendix A.2):
+                                   kappa = tau / max_j bp_j, bp_j the largest
+                                   breakpoint (y_i - bound_i)/a_ji of row j;
+                                   kappa = 0 when no breakpoint is positive     */
   void* x;                      /* device [n] output; must not alias y or A    */
   uint32_t* free_mask;          /* optional device [(n+31)/32]: bit i set when
                                    lo <= (y - A^T lam)_i <= hi; NULL to skip    */
@@ -151,6 +157,7 @@ typedef struct {
   int32_t row_outcome[PGDTO_MAX_BLOCKS];
   double res_inf;        /* max_j scaled KKT residual at exit                */
   double lambda_width;   /* final bracket width (1-D searches, max)          */
+  double kappa;          /* regularization used: 2/C, or the automatic value */
 } pgdto_result;
 
 typedef struct {

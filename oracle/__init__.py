@@ -14,6 +14,8 @@ Contents
                               dual maximization, active-pattern polish, KKT check
   projection.kkt_certificate  KKT residuals of eq. (rkkt1)-(rkkt11)
   projection.brute_force      enumeration of element states and active rows
+  projection.auto_C           the penalty bounding constraint violation by tau
+                              (Appendix A.2), from the largest breakpoint
   literal.alg1_bisection      Algorithm 1 as printed (float64), for iteration counts
   literal.alg2_newton         Algorithm 2 (Stage 1 + semismooth Newton), float64
   pgd.pgd_step                one step of Algorithm 3 around the projection
@@ -23,10 +25,11 @@ quantities left unpinned are the literal algorithms' iteration counts
 ("parity unpinned": they are reported, never compared).
 """
 from .projection import (clip_map, h_map, exact_single, project, coupled,
-                         kkt_certificate, brute_force, row_scale, OracleResult)
+                         kkt_certificate, brute_force, row_scale, OracleResult,
+                         largest_breakpoint, auto_C)
 from .pgd import pgd_step, step_size, cg_beta, PgdParams
 from . import literal
 
 __all__ = ["clip_map", "h_map", "exact_single", "project", "coupled", "kkt_certificate",
-           "brute_force", "row_scale", "OracleResult", "pgd_step", "step_size", "cg_beta",
+           "brute_force", "row_scale", "OracleResult", "largest_breakpoint", "auto_C", "pgd_step", "step_size", "cg_beta",
            "PgdParams", "literal"]

@@ -321,6 +321,42 @@ class OracleResult:
     kappa: float
 
 
+def largest_breakpoint(y, a, lo, hi):
+    """Largest multiplier at which an element of one row reaches the bound it
+    is driven to: (y_i - lo)/a_i for a_i > 0, (y_i - hi)/a_i for a_i < 0,
+    elements with a_i = 0 left out (Appendix A.1; the end of Algorithm 1's
+    bracket, -y_l in the paper's sign).  -inf for a row without coefficients."""
+    y = np.asarray(y, dtype=np.float64)
+    a = np.asarray(a, dtype=np.float64)
+    best = -math.inf
+    for yi, ai in zip(y, a):
+        if ai > 0.0:
+            best = max(best, (yi - lo) / ai)
+        elif ai < 0.0:
+            best = max(best, (yi - hi) / ai)
+    return best
+
+
+def auto_C(kind, y, A, lo, hi, tau, offsets=None):
+    """The penalty of Appendix A.2 that bounds the constraint violation by
+    tau: C = 2 bp / tau with bp the largest breakpoint over all rows (the
+    paper writes the smallest breakpoint in its sign, y <= 0, whose magnitude
+    this is), so kappa = 2/C = tau / bp.  inf (kappa = 0) when no breakpoint
+    is positive."""
+    y = np.asarray(y, dtype=np.float64)
+    if kind == "independent":
+        c = np.asarray(A, dtype=np.float64).reshape(-1)
+        rows = [(y[int(offsets[j]):int(offsets[j + 1])], c[int(offsets[j]):int(offsets[j + 1])])
+                for j in range(len(offsets) - 1)]
+    else:
+        Ad = np.atleast_2d(np.asarray(A, dtype=np.float64))
+        rows = [(y, Ad[j]) for j in range(Ad.shape[0])]
+    bp = max(largest_breakpoint(yy, aa, lo, hi) for yy, aa in rows)
+    if not (bp > 0.0) or not math.isfinite(bp):
+        return math.inf
+    return 2.0 * bp / tau
+
+
 def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None):
     """Projection of y onto {lo <= x <= hi, A x <= b} in the regularized form
     with kappa = 2/C (kappa = 0 when C is infinite).

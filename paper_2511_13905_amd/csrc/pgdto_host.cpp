@@ -185,7 +185,9 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   if ((need_y && !aligned16(pr->y)) || !aligned16(pr->A) || !aligned16(pr->x)) return PGDTO_ERR_ARG;
   if (pr->free_mask && ((uintptr_t)pr->free_mask & 3u)) return PGDTO_ERR_ARG;
   if (!isfinite(pr->lo) || !isfinite(pr->hi) || !(pr->lo < pr->hi)) return PGDTO_ERR_ARG;
-  if (!(pr->C > 0.0)) return PGDTO_ERR_ARG;     // NaN and non-positive rejected; INFINITY allowed
+  // NaN, 0 and -INFINITY rejected; INFINITY allowed; C < 0 asks for the
+  // automatic penalty with tolerance -C
+  if (!(pr->C > 0.0) && !(pr->C < 0.0 && isfinite(pr->C))) return PGDTO_ERR_ARG;
   size_t abytes = (size_t)n * esz;
   if (pr->kind != PGDTO_INDEPENDENT) {
     if (pr->m > 1) {
@@ -210,7 +212,8 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   d.free_mask = pr->free_mask;
   d.lo = pr->lo;
   d.hi = pr->hi;
-  d.kappa = isinf(pr->C) ? 0.0 : 2.0 / pr->C;
+  d.auto_tau = pr->C < 0.0 ? -pr->C : 0.0;
+  d.kappa = (pr->C < 0.0 || isinf(pr->C)) ? 0.0 : 2.0 / pr->C;
   d.tol_b = pp->tol_b;
   d.tol_n = pp->tol_n;
   d.c1 = pp->c1;

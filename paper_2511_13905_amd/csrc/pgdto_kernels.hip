@@ -624,6 +624,19 @@ __device__ __forceinline__ void search_update(Search& S, int s, double f0sum, do
   search_pick(S, s, mode, lean);
 }
 
+// Automatic penalty (Appendix A.2): with tau the tolerated constraint
+// violation, C = 2 bp / tau, i.e. kappa = tau / bp, bp the largest breakpoint
+// over the rows (the end of every row's bracket).  Rows with a non-finite or
+// non-positive breakpoint do not count; with none left kappa = 0.
+__device__ __forceinline__ double auto_kappa(double tau, const double* bp, int stride, int rows) {
+  double mx = 0.0;
+  for (int j = 0; j < rows; ++j) {
+    const double v = bp[j * stride];
+    if (isfinite(v) && v > mx) mx = v;
+  }
+  return mx > 0.0 ? tau / mx : 0.0;
+}
+
 // Control parameters, copied once into LDS so that no reference to the
 // kernel argument escapes into out-of-line functions (it would be copied to
 // private memory per lane).
@@ -698,7 +711,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   const int tid = threadIdx.x;
   const int G = wg_num(d);
   const int wid = wg_id(d);
-  const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi), kappa = d.kappa;
+  const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi);
+  double kappa = d.kappa;           // the automatic penalty replaces it after the zero pass
 
   if (tid == 0) {
     sh.phase = PH_ZERO;
@@ -1123,6 +1137,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 
     // ---------------- control (identical in every workgroup)
     if (ph == PH_ZERO) {
+      if (d.auto_tau > 0.0) kappa = auto_kappa(d.auto_tau, &sh.tot[2], 6, d.nseg);
       for (int s = tid; s < d.nseg; s += BLOCK) {
         const double* t = &sh.tot[s * 6];
         double scale = t[4] * fmax(fabs(lo), fabs(hi));
@@ -1186,6 +1201,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           R->n_free = (int64_t)nfree;
           R->res_inf = 0.0;
           R->lambda_width = wmax;
+          R->kappa = kappa;
           if (d.pgd) {
             pgdto_pgd_out* P = (pgdto_pgd_out*)d.result;
             P->alpha = sh.pg.alpha;
@@ -1561,7 +1577,8 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
   const int tid = threadIdx.x;
   const int G = wg_num(d);
   const int wid = wg_id(d);
-  const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi), kappa = d.kappa;
+  const double lo = __builtin_canonicalize(d.lo), hi = __builtin_canonicalize(d.hi);
+  double kappa = d.kappa;           // the automatic penalty replaces it after the zero pass
 
   if (tid == 0) {
     sh.phase = d.pgd ? PH_PGD_R : PH_ZERO;
@@ -1904,6 +1921,10 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         sh.phase = PH_ZERO;
       }
     } else if (ph == PH_ZERO) {
+      if (d.auto_tau > 0.0) {
+        kappa = auto_kappa(d.auto_tau, &t[2 * M], 1, M);
+        if (tid == 0) sh.P.kappa = kappa;     // the Newton control reads it from LDS
+      }
       if (tid < M) {
         const int j = tid;
         double scale = t[4 * M + j] * fmax(fabs(lo), fabs(hi));
@@ -2045,6 +2066,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           double wmax = 0.0;
           for (int j = 0; j < M; ++j) wmax = fmax(wmax, sh.S.width[j]);
           R->lambda_width = wmax;
+          R->kappa = kappa;
           if (d.pgd) {
             pgdto_pgd_out* P = (pgdto_pgd_out*)d.result;
             P->alpha = sh.pg.alpha;

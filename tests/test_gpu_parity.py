@@ -203,6 +203,31 @@ def test_bisect_rule(ctx):
     check(q, x, r, orc(q), fm)
 
 
+@pytest.mark.parametrize("kind", ["single", "independent", "coupled", "coupled-infeasible"])
+def test_automatic_penalty(ctx, kind):
+    """C < 0 asks for Appendix A.2's penalty C = 2 bp / tau (tau = -C) from
+    the largest breakpoint of the zero pass; the oracle takes the same C from
+    its own exact breakpoints."""
+    import dataclasses
+    gen = {"single": lambda: I.compliance_3d(2, n=70001),
+           "independent": lambda: I.multi_material(1, fields=4, n_per=20001),
+           "coupled": lambda: I.volume_com(0, grid=(96, 48)),
+           "coupled-infeasible": lambda: I.volume_com(1, grid=(64, 32))}[kind]
+    p0 = gen()
+    tau = 1e-6 * float(np.max(np.abs(p0.b)))
+    p = dataclasses.replace(p0, C=-tau)
+    say("automatic penalty", kind, p.n, tau)
+    x, r, fm = run(ctx, p)
+    C_or = oracle.auto_C(p.kind, p.y, p.A, p.lo, p.hi, tau, p.offsets)
+    assert math.isfinite(C_or)
+    assert r["kappa"] == pytest.approx(2.0 / C_or, rel=1e-12)
+    ref = oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, C_or, p.offsets)
+    check(dataclasses.replace(p0, C=C_or), x, r, ref, fm)
+    if kind in ("single", "independent"):
+        for j in range(p.m):
+            assert r["resid"][j] <= tau * (1 + 1e-6) + 1e-6 * abs(p.b[j])
+
+
 def test_infeasible_single_row(ctx):
     rng = np.random.default_rng(12)
     n = 5000

@@ -246,6 +246,42 @@ def test_regularization_limit():
     assert errs[2] < 1e-9
 
 
+def test_auto_C_hand_example():
+    """Appendix A.2's penalty C = 2 bp / tau on breakpoints worked by hand:
+    y = (0.5, 0.2), a = (1, -2), box [0, 1]: element 1 reaches 0 at
+    lam = 0.5/1, element 2 reaches 1 at lam = (0.2 - 1)/(-2) = 0.4; the
+    largest is 0.5, so C = 2 * 0.5 / 1e-3 = 1000."""
+    assert P.largest_breakpoint([0.5, 0.2], [1.0, -2.0], 0.0, 1.0) == 0.5
+    assert oracle.auto_C("single", [0.5, 0.2], [[1.0, -2.0]], 0.0, 1.0, 1e-3) == 1000.0
+    # two blocks: the largest over blocks (block 2: (0.9 - 0)/0.5 = 1.8)
+    assert oracle.auto_C("independent", [0.5, 0.2, 0.9], [1.0, -2.0, 0.5], 0.0, 1.0, 1e-3,
+                         offsets=[0, 2, 3]) == pytest.approx(2 * 1.8 / 1e-3, rel=1e-15)
+    # coupled rows: the largest over rows
+    assert oracle.auto_C("coupled", [0.5, 0.2], [[1.0, -2.0], [0.25, 0.0]], 0.0, 1.0, 1e-3) == 4000.0
+    # no positive breakpoint (every element already at the bound it moves to): kappa = 0
+    assert oracle.auto_C("single", [0.0, 1.0], [[1.0, -1.0]], 0.0, 1.0, 1e-3) == math.inf
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_auto_C_bounds_violation(seed):
+    """With C = 2 bp / tau the regularized optimum violates a feasible row by
+    at most tau (the bound stated with the penalty in Appendix A.2): the
+    multiplier stays below bp, and the violation is kappa lam."""
+    rng = np.random.default_rng(40 + seed)
+    n = 3000
+    y = rng.uniform(-0.2, 1.2, n)
+    a = -(np.abs(rng.standard_normal(n)) + 0.01)
+    lam0 = rng.uniform(0.2, 0.8)
+    b = float(a @ np.clip(y - lam0 * a, 0.0, 1.0))        # planted, feasible
+    tau = 10.0 ** rng.uniform(-6, -2) * abs(b)
+    C = oracle.auto_C("single", y, a.reshape(1, -1), 0.0, 1.0, tau)
+    r = oracle.project("single", y, a.reshape(1, -1), [b], 0.0, 1.0, C)
+    viol = r.resid[0]
+    assert 0.0 <= viol <= tau * (1 + 1e-9), (viol, tau)
+    assert r.slack[0] == pytest.approx(viol, rel=1e-6, abs=1e-12 * abs(b))
+    assert r.lam[0] <= P.largest_breakpoint(y, a, 0.0, 1.0)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_kkt_certificates_of_workloads(seed):
     """Every workload class is certified by the KKT residuals (eq. rkkt1-rkkt11)."""
