@@ -71,8 +71,13 @@ def row_scale(A, lo, hi):
 
 # ------------------------------------------------------------- one row (m = 1)
 
-def exact_single(y, a, b, lo, hi, kappa=0.0):
+def exact_single(y, a, b, lo, hi, kappa=0.0, eq=False):
     """Exact multiplier of the one-row projection.
+
+    eq=True: the row is an equality a.x = b (Sec. 3.2, the note on equality
+    constraints: always active, multiplier of either sign).  When phi(0) < 0
+    the row a.x >= b, i.e. (-a).x <= -b, is the active one: it is solved as
+    such and its multiplier negated (x = clip(y - lam a) with lam < 0).
 
     Appendix A.1 (eq. Gamma): with one row, phi(lam) = sum_i a_i clip(y_i - lam
     a_i) - b - kappa lam is piecewise linear and nonincreasing in lam (the
@@ -102,6 +107,13 @@ def exact_single(y, a, b, lo, hi, kappa=0.0):
         s = fsum(a * x) if exact else float(np.sum(a * x))
         return s - b - kappa * lam
 
+    if eq:
+        p0 = phi(0.0, exact=True)
+        if p0 == 0.0:
+            return 0.0, "converged"
+        if p0 < 0.0:
+            lam, out = exact_single(y, -a, -b, lo, hi, kappa)
+            return -lam, out
     if phi(0.0, exact=True) <= 0.0:
         return 0.0, "inactive"
     nz = a != 0.0
@@ -151,16 +163,19 @@ def _dual_value_grad(lam, y, A, b, lo, hi, kappa):
     return q, Ax - b - kappa * lam
 
 
-def _polish(lam, y, A, b, lo, hi, kappa, max_iter=200):
+def _polish(lam, y, A, b, lo, hi, kappa, max_iter=200, eq=None):
     """Fix the element pattern (lower / free / upper) and the active rows at the
     current lam and solve the resulting linear system for lam exactly:
 
         (A_SF A_SF^T + kappa I) lam_S = A_SF y_F + lo A_SL 1 + hi A_SU 1 - b_S
 
     which is h_S(lam) = 0 written out for that pattern (eq. h with x from
-    eq. delta_y_robust).  Repeat until the pattern no longer changes."""
+    eq. delta_y_robust).  Repeat until the pattern no longer changes.
+    Equality rows (eq) are always in S and keep multipliers of either sign."""
     m = A.shape[0]
-    lam = np.maximum(np.asarray(lam, dtype=np.float64), 0.0)
+    eq = np.zeros(m, dtype=bool) if eq is None else np.asarray(eq, dtype=bool)
+    lam = np.asarray(lam, dtype=np.float64)
+    lam = np.where(eq, lam, np.maximum(lam, 0.0))
     seen = set()
     for _ in range(max_iter):
         x, z = clip_map(y, A, lam, lo, hi)
@@ -168,7 +183,7 @@ def _polish(lam, y, A, b, lo, hi, kappa, max_iter=200):
         L = z < lo
         U = z > hi
         h = np.array([fsum(A[j] * x) - b[j] - kappa * lam[j] for j in range(m)])
-        S = (lam > 0.0) | (h > 0.0)
+        S = eq | (lam > 0.0) | (h > 0.0)
         key = (S.tobytes(), np.packbits(F).tobytes(), np.packbits(L).tobytes())
         new = np.zeros(m)
         if S.any():
@@ -194,7 +209,7 @@ def _polish(lam, y, A, b, lo, hi, kappa, max_iter=200):
                 except np.linalg.LinAlgError:
                     break
             new[S] = sol
-        new = np.maximum(new, 0.0)
+        new = np.where(eq, new, np.maximum(new, 0.0))
         if np.array_equal(new, lam) or key in seen:
             lam = new
             break
@@ -203,39 +218,43 @@ def _polish(lam, y, A, b, lo, hi, kappa, max_iter=200):
     return lam
 
 
-def coupled(y, A, b, lo, hi, kappa, lam0=None):
+def coupled(y, A, b, lo, hi, kappa, lam0=None, eq=None):
     """Multiplier of the regularized multi-row projection (Appendix A.2).
 
     1. Maximize the concave dual q over lam >= 0 (L-BFGS-B on -q with Jacobi
        scaling; gradient h), which is a plain way to approach lam*.
     2. Polish: solve the fixed-pattern linear system exactly (``_polish``).
     Correctness is established independently by ``kkt_certificate`` (the
-    solution is unique when kappa > 0: Appendix A.2, eq. reg_jacobian)."""
+    solution is unique when kappa > 0: Appendix A.2, eq. reg_jacobian).
+    Equality rows (eq, Sec. 3.2): the dual variable is free in sign."""
     y = np.asarray(y, dtype=np.float64)
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     b = np.asarray(b, dtype=np.float64)
     m = A.shape[0]
+    eq = np.zeros(m, dtype=bool) if eq is None else np.asarray(eq, dtype=bool)
     h0 = h_map(y, A, b, np.zeros(m), lo, hi, kappa)
-    if np.all(h0 <= 0.0):
+    if np.all(h0[~eq] <= 0.0) and np.all(h0[eq] == 0.0):
         return np.zeros(m)
     d = np.array([float(np.dot(A[j], A[j])) for j in range(m)]) + kappa
     d[d == 0.0] = 1.0
-    start = np.zeros(m) if lam0 is None else np.maximum(np.asarray(lam0, float), 0.0)
+    start = np.zeros(m) if lam0 is None else np.asarray(lam0, float)
+    start = np.where(eq, start, np.maximum(start, 0.0))
     lam = start
     if _sp_minimize is not None:
         def f(mu):
             q, g = _dual_value_grad(mu / d, y, A, b, lo, hi, kappa)
             return -q, -g / d
         res = _sp_minimize(f, start * d, jac=True, method="L-BFGS-B",
-                           bounds=[(0.0, None)] * m,
+                           bounds=[(None, None) if e else (0.0, None) for e in eq],
                            options={"maxiter": 5000, "ftol": 1e-16, "gtol": 1e-14, "maxcor": 20})
-        lam = np.maximum(res.x / d, 0.0)
-    return _polish(lam, y, A, b, lo, hi, kappa)
+        lam = res.x / d
+        lam = np.where(eq, lam, np.maximum(lam, 0.0))
+    return _polish(lam, y, A, b, lo, hi, kappa, eq=eq)
 
 
 # ------------------------------------------------------------ KKT certificate
 
-def kkt_certificate(y, A, b, lo, hi, kappa, lam, x=None):
+def kkt_certificate(y, A, b, lo, hi, kappa, lam, x=None, eq=None):
     """Scaled residuals of the KKT system of the regularized problem
     (eqs. rkkt1-rkkt11, reduced as in Appendix A.2 to conditions on lam):
 
@@ -243,18 +262,22 @@ def kkt_certificate(y, A, b, lo, hi, kappa, lam, x=None):
       dual    -min_j lam_j                       (lam >= 0)
       primal  max_j max(h_j, 0) / sigma_j        (h <= 0)
       compl   max_j |lam_j h_j| / (sigma_j max(1, lam_j))
+    Equality rows (eq): lam_j of either sign, primal |h_j| / sigma_j, no
+    complementarity term.
     """
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     lam = np.asarray(lam, dtype=np.float64).reshape(-1)
+    eq = np.zeros(lam.size, dtype=bool) if eq is None else np.asarray(eq, dtype=bool)
     xl, _ = clip_map(y, A, lam, lo, hi)
     sig = row_scale(A, lo, hi)
     sig[sig == 0.0] = 1.0
     h = h_map(y, A, b, lam, lo, hi, kappa)
+    ine = ~eq
     out = {
         "map": 0.0 if x is None else float(np.max(np.abs(np.asarray(x, float) - xl), initial=0.0)),
-        "dual": float(max(0.0, -np.min(lam))),
-        "primal": float(np.max(np.maximum(h, 0.0) / sig)),
-        "compl": float(np.max(np.abs(lam * h) / (sig * np.maximum(1.0, lam)))),
+        "dual": float(max(0.0, -np.min(lam[ine], initial=0.0))),
+        "primal": float(np.max(np.where(eq, np.abs(h), np.maximum(h, 0.0)) / sig)),
+        "compl": float(np.max(np.abs(lam[ine] * h[ine]) / (sig[ine] * np.maximum(1.0, lam[ine])), initial=0.0)),
     }
     out["max"] = max(out.values())
     return out
@@ -262,22 +285,26 @@ def kkt_certificate(y, A, b, lo, hi, kappa, lam, x=None):
 
 # ------------------------------------------------------------ brute force
 
-def brute_force(y, A, b, lo, hi, kappa, tol=1e-9):
+def brute_force(y, A, b, lo, hi, kappa, tol=1e-9, eq=None):
     """Enumerate every element state in {lower, upper, free}^n and every set S
     of rows held at equality, solve the KKT equations of that combination, and
     keep the combinations that satisfy all sign conditions (Appendix A: the
     case analysis behind eq. delta_y plus conditions 1-3 on y).  Returns the
     list of surviving x vectors (uniqueness says they all coincide).
-    For n <= 9 and m <= 3 only."""
+    Equality rows (eq) belong to every S and may take multipliers of either
+    sign.  For n <= 9 and m <= 3 only."""
     y = np.asarray(y, dtype=np.float64)
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     b = np.asarray(b, dtype=np.float64)
     m, n = A.shape
+    eq = np.zeros(m, dtype=bool) if eq is None else np.asarray(eq, dtype=bool)
     states = np.array(list(itertools.product((0, 1, 2), repeat=n)))   # 0 L, 1 U, 2 F
     survivors = []
     for r in range(m + 1):
         for S in itertools.combinations(range(m), r):
             S = list(S)
+            if any(eq[j] and j not in S for j in range(m)):
+                continue
             for st in states:
                 F = st == 2
                 xf = np.where(st == 0, lo, np.where(st == 1, hi, 0.0))
@@ -291,7 +318,7 @@ def brute_force(y, A, b, lo, hi, kappa, tol=1e-9):
                     lam[S] = np.linalg.solve(M, rhs)
                 z = y - A.T @ lam
                 x = np.where(F, z, xf)
-                if np.any(lam < -tol):
+                if np.any(lam[~eq] < -tol):
                     continue
                 if np.any(z[st == 0] > lo + tol) or np.any(z[st == 1] < hi - tol):
                     continue
@@ -357,9 +384,10 @@ def auto_C(kind, y, A, lo, hi, tau, offsets=None):
     return 2.0 * bp / tau
 
 
-def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None):
+def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None, eq=None):
     """Projection of y onto {lo <= x <= hi, A x <= b} in the regularized form
-    with kappa = 2/C (kappa = 0 when C is infinite).
+    with kappa = 2/C (kappa = 0 when C is infinite).  eq (optional, one flag
+    per row or block): rows held at equality, a_j.x = b_j (Sec. 3.2).
 
     kind "single": one dense row (Algorithm 1's problem).
     kind "independent": disjoint blocks, A[i] is the coefficient of element i in
@@ -369,6 +397,8 @@ def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None):
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     kappa = 0.0 if math.isinf(C) else 2.0 / C
     n = y.size
+    m_rows = b.size
+    eq = np.zeros(m_rows, dtype=bool) if eq is None else np.asarray(eq, dtype=bool).reshape(-1)
     if kind == "independent":
         c = np.asarray(A, dtype=np.float64).reshape(-1)
         m = b.size
@@ -378,7 +408,7 @@ def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None):
         z = np.empty(n)
         for j in range(m):
             s, e = int(offsets[j]), int(offsets[j + 1])
-            lj, oj = exact_single(y[s:e], c[s:e], b[j], lo, hi, kappa)
+            lj, oj = exact_single(y[s:e], c[s:e], b[j], lo, hi, kappa, eq=bool(eq[j]))
             lam[j] = lj
             outcome.append(oj)
             z[s:e] = y[s:e] - lj * c[s:e]
@@ -389,11 +419,11 @@ def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None):
         Ad = np.atleast_2d(np.asarray(A, dtype=np.float64))
         m = Ad.shape[0]
         if kind == "single":
-            lj, oj = exact_single(y, Ad[0], b[0], lo, hi, kappa)
+            lj, oj = exact_single(y, Ad[0], b[0], lo, hi, kappa, eq=bool(eq[0]))
             lam = np.array([lj])
             outcome = [oj]
         elif kind == "coupled":
-            lam = coupled(y, Ad, b, lo, hi, kappa)
+            lam = coupled(y, Ad, b, lo, hi, kappa, eq=eq)
             outcome = ["inactive" if np.all(lam == 0.0) else "converged"]
         else:
             raise ValueError(kind)

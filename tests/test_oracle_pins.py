@@ -282,6 +282,87 @@ def test_auto_C_bounds_violation(seed):
     assert r.lam[0] <= P.largest_breakpoint(y, a, 0.0, 1.0)
 
 
+@pytest.mark.parametrize("kappa", [0.0, 0.5])
+def test_equality_row_closed_form(kappa):
+    """An equality row a.x = b (Sec. 3.2: always active, multiplier of either
+    sign) on a point that stays inside the box: x = y - lam a with
+    a.(y - lam a) - b - kappa lam = 0, so lam = (a.y - b) / (a.a + kappa),
+    negative when b lies above a.y."""
+    n = 50
+    y = 0.3 + 0.4 * np.arange(n) / n
+    a = np.full(n, 1.0 / n)
+    for shift in (+0.02, -0.02):                 # b above a.y (lam < 0), below (lam > 0)
+        b = float(a @ y) + shift
+        lam_cf = (float(a @ y) - b) / (float(a @ a) + kappa)
+        lam, out = P.exact_single(y, a, b, 0.0, 1.0, kappa, eq=True)
+        assert out == "converged"
+        assert lam == pytest.approx(lam_cf, rel=1e-12)
+        assert np.sign(lam) == -np.sign(shift)
+        C = math.inf if kappa == 0.0 else 2.0 / kappa
+        r = oracle.project("single", y, a.reshape(1, -1), [b], 0.0, 1.0, C, eq=[True])
+        assert r.lam[0] == pytest.approx(lam_cf, rel=1e-12)
+        rc = oracle.project("coupled", y, a.reshape(1, -1), [b], 0.0, 1.0, C, eq=[True])
+        assert rc.lam[0] == pytest.approx(lam_cf, rel=1e-9)
+    # an inequality row with b above a.y is inactive instead
+    r = oracle.project("single", y, a.reshape(1, -1), [float(a @ y) + 0.02], 0.0, 1.0)
+    assert r.lam[0] == 0.0 and r.outcome[0] == "inactive"
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_equality_rows_brute_force(seed):
+    """Equality rows against enumeration of element states and active sets
+    in which every equality row is held (tiny n)."""
+    rng = np.random.default_rng(60 + seed)
+    n, m = 6, 1 + seed % 2
+    y = rng.uniform(-0.3, 1.3, n)
+    A = rng.standard_normal((m, n))
+    xs = rng.uniform(0.1, 0.9, n)
+    b = A @ xs + rng.uniform(-0.3, 0.3, m)          # reachable targets, either side of A.clip(y)
+    eq = np.array([True] + [bool(rng.integers(0, 2)) for _ in range(m - 1)])
+    kappa = [0.0, 0.3][seed % 2]
+    C = math.inf if kappa == 0.0 else 2.0 / kappa
+    kind = "single" if m == 1 else "coupled"
+    r = oracle.project(kind, y, A, b, 0.0, 1.0, C, eq=eq)
+    surv = P.brute_force(y, A, b, 0.0, 1.0, kappa, eq=eq)
+    assert surv, "no KKT point found by enumeration"
+    for xb in surv:
+        np.testing.assert_allclose(r.x, xb, atol=1e-8)
+    cert = P.kkt_certificate(y, A, b, 0.0, 1.0, kappa, r.lam, r.x, eq=eq)
+    assert cert["max"] < 1e-9, cert
+    for j in np.flatnonzero(eq):
+        assert abs(r.resid[j] - kappa * r.lam[j]) < 1e-9
+
+
+def test_equality_row_is_two_opposite_inequalities():
+    """Unregularized, {a.x = b} is {a.x <= b} and {-a.x <= -b} together: the
+    projections coincide (enumeration over the two-row form)."""
+    rng = np.random.default_rng(71)
+    n = 7
+    for _ in range(4):
+        y = rng.uniform(-0.3, 1.3, n)
+        a = rng.standard_normal(n)
+        b = float(a @ rng.uniform(0.1, 0.9, n))
+        r = oracle.project("single", y, a.reshape(1, -1), [b], 0.0, 1.0, eq=[True])
+        surv = P.brute_force(y, np.vstack([a, -a]), np.array([b, -b]), 0.0, 1.0, 0.0)
+        assert surv
+        for xb in surv:
+            np.testing.assert_allclose(r.x, xb, atol=1e-8)
+
+
+def test_equality_blocks_are_separate_rows():
+    """Independent blocks with equality flags = each block projected alone."""
+    p = I.multi_material(3, fields=3, n_per=4000)
+    eq = [True, False, True]
+    b = p.b.copy()
+    b[0] *= 1.5                                      # above a.clip(y) for the first field
+    r = oracle.project("independent", p.y, p.A, b, p.lo, p.hi, offsets=p.offsets, eq=eq)
+    for j in range(3):
+        s, e = int(p.offsets[j]), int(p.offsets[j + 1])
+        lj, _ = P.exact_single(p.y[s:e], p.A[s:e], b[j], p.lo, p.hi, 0.0, eq=eq[j])
+        assert r.lam[j] == lj
+    assert r.resid[0] == pytest.approx(0.0, abs=1e-12 * abs(b[0]) + 1e-15)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_kkt_certificates_of_workloads(seed):
     """Every workload class is certified by the KKT residuals (eq. rkkt1-rkkt11)."""
