@@ -123,6 +123,12 @@ typedef struct {
   void* x;                      /* device [n] output; must not alias y or A    */
   uint32_t* free_mask;          /* optional device [(n+31)/32]: bit i set when
                                    lo <= (y - A^T lam)_i <= hi; NULL to skip    */
+  uint64_t eq_mask;             /* bit j set: row / block j is an equality
+                                   a_j.x = b_j (Sec. 3.2, the note on equality
+                                   constraints: always active, multiplier of
+                                   either sign, lambda[j] < 0 when the row is
+                                   raised to its target); 0: all A x <= b.
+                                   Bits at or above m: PGDTO_ERR_ARG           */
 } pgdto_problem;
 
 typedef struct {
@@ -151,7 +157,7 @@ typedef struct {
   int32_t m;             /* rows / blocks                                    */
   int32_t error;         /* 0, or PGDTO_ERR_TIMEOUT if a device wait expired */
   int64_t n_free;        /* elements with lo <= z_i <= hi                    */
-  double lambda[PGDTO_MAX_BLOCKS];  /* multipliers (>= 0)                    */
+  double lambda[PGDTO_MAX_BLOCKS];  /* multipliers (>= 0; equality rows: any sign) */
   double resid[PGDTO_MAX_BLOCKS];   /* a_j.x - b_j with x as stored          */
   double slack[PGDTO_MAX_BLOCKS];   /* kappa lam_j (eq. s_y_robust)          */
   int32_t row_outcome[PGDTO_MAX_BLOCKS];

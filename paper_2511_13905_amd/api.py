@@ -73,10 +73,20 @@ class _Keep:
         return arr
 
 
+def eq_mask_of(eq) -> int:
+    """Equality rows as a bit mask: None, an int mask, or one flag per row/block."""
+    if eq is None:
+        return 0
+    if isinstance(eq, int):
+        return eq
+    return sum(1 << j for j, e in enumerate(eq) if e)
+
+
 def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, free_mask=None,
-                   keep: _Keep | None = None, copy_ok: bool = True):
+                   keep: _Keep | None = None, copy_ok: bool = True, eq=None):
     """Fill a pgdto_problem from torch tensors; returns (struct, x, A_used).
-    copy_ok=False: raise instead of copying A into 16-byte aligned rows."""
+    copy_ok=False: raise instead of copying A into 16-byte aligned rows.
+    eq: rows / blocks held at equality (flags or a bit mask)."""
     keep = keep or _Keep()
     k = N.KINDS[kind] if isinstance(kind, str) else int(kind)
     if y is not None and not y.is_contiguous():
@@ -113,6 +123,7 @@ def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, 
     s.C = float(C_pen)
     s.x = x.data_ptr()
     s.free_mask = free_mask.data_ptr() if free_mask is not None else None
+    s.eq_mask = eq_mask_of(eq)
     return s, x, A_used
 
 
@@ -156,10 +167,10 @@ class Context:
 
     # ------------------------------------------------------------ projection
     def project(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None,
-                params: N.Params | dict | None = None, stream=None):
+                params: N.Params | dict | None = None, stream=None, eq=None):
         """pgdto_project: returns (x, result dict).  Blocks until done."""
         keep = _Keep()
-        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep)
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         r = N.Result()
         st = N.lib().pgdto_project(self.h, C_byref(s), C_byref(p), C_byref(r), _stream(self.device, stream))
@@ -167,11 +178,11 @@ class Context:
         return x, r.to_dict()
 
     def project_async(self, kind, y, A, b, lo, hi, result_buf: torch.Tensor, C=math.inf, offsets=None,
-                      x=None, free_mask=None, params=None, stream=None):
+                      x=None, free_mask=None, params=None, stream=None, eq=None):
         """pgdto_project_async: enqueue only; the result struct lands in result_buf
         (uint8 device tensor of at least sizeof(pgdto_result) bytes)."""
         keep = _Keep()
-        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep)
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         st = N.lib().pgdto_project_async(self.h, C_byref(s), C_byref(p), result_buf.data_ptr(),
                                          _stream(self.device, stream))
@@ -180,9 +191,9 @@ class Context:
 
     # ------------------------------------------------------------ Alg. 3 step
     def _pgd_struct(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                    hyper, keep, copy_ok=True):
+                    hyper, keep, copy_ok=True, eq=None):
         s, x, _A = problem_struct(kind, None, A, None, lo, hi, C, offsets, x if x is not None else
-                                  torch.empty_like(rho), None, keep, copy_ok=copy_ok)
+                                  torch.empty_like(rho), None, keep, copy_ok=copy_ok, eq=eq)
         a = N.PgdArgs()
         N.lib().pgdto_pgd_args_default(C_byref(a))
         a.proj = s
@@ -201,12 +212,12 @@ class Context:
         return a, x
 
     def pgd_step(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf,
-                 offsets=None, x=None, params=None, stream=None, **hyper):
+                 offsets=None, x=None, params=None, stream=None, eq=None, **hyper):
         """pgdto_pgd_step: one Alg. 3 body.  d is updated in place (d_{t-1} -> d_t);
         returns (rho_{t+1}, out dict)."""
         keep = _Keep()
         a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                hyper, keep)
+                                hyper, keep, eq=eq)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         out = N.PgdOut()
         st = N.lib().pgdto_pgd_step(self.h, C_byref(a), C_byref(p), C_byref(out), _stream(self.device, stream))
@@ -269,9 +280,10 @@ class Batch:
         _check(N.lib().pgdto_batch_shape(self.h, C.byref(s), C.byref(w)), "pgdto_batch_shape")
         return s.value, w.value
 
-    def submit(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None, params=None) -> int:
+    def submit(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None, params=None,
+               eq=None) -> int:
         keep = _Keep()
-        s, x, A_used = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, copy_ok=False)
+        s, x, A_used = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, copy_ok=False, eq=eq)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         t = C_u64()
         _check(N.lib().pgdto_batch_submit(self.h, C_byref(s), C_byref(p), C_byref(t)), "pgdto_batch_submit")

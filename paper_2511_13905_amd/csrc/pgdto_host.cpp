@@ -212,6 +212,8 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   d.free_mask = pr->free_mask;
   d.lo = pr->lo;
   d.hi = pr->hi;
+  if (pr->m < 64 && (pr->eq_mask >> pr->m) != 0) return PGDTO_ERR_ARG;
+  d.eq_mask = pr->eq_mask;
   d.auto_tau = pr->C < 0.0 ? -pr->C : 0.0;
   d.kappa = (pr->C < 0.0 || isinf(pr->C)) ? 0.0 : 2.0 / pr->C;
   d.tol_b = pp->tol_b;

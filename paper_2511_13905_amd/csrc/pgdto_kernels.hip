@@ -152,12 +152,12 @@ __device__ __forceinline__ double clampd(double z, double lo, double hi) { retur
 // correctly rounded one at a third of the cost of a full division.  Only the
 // largest breakpoint is used, as the end of the search bracket (the smallest
 // multiplier at which every element is saturated).
-__device__ __forceinline__ double breakpoint(double y, double av, double bound) {
+__device__ __forceinline__ double recip(double av) {
   double r = __builtin_amdgcn_rcp(av);
   r = fma(r, fma(-av, r, 1.0), r);
-  r = fma(r, fma(-av, r, 1.0), r);
-  return (y - bound) * r;
+  return fma(r, fma(-av, r, 1.0), r);
 }
+__device__ __forceinline__ double breakpoint(double y, double av, double bound) { return (y - bound) * recip(av); }
 
 // ------------------------------------------------------------------ reductions
 
@@ -642,13 +642,13 @@ __device__ __forceinline__ double auto_kappa(double tau, const double* bp, int s
 // private memory per lane).
 struct CtlParams {
   double kappa, tol_n, tol_b, c1, c2;
-  int32_t max_newton, max_ls, max_search, ncp, search, pad;
+  int32_t max_newton, max_ls, max_search, ncp, search, eq;   // eq: equality-row bits
 };
 
 __device__ __forceinline__ void load_ctl(const Desc& d, CtlParams& P) {
   P.kappa = d.kappa; P.tol_n = d.tol_n; P.tol_b = d.tol_b; P.c1 = d.c1; P.c2 = d.c2;
   P.max_newton = d.max_newton; P.max_ls = d.max_ls; P.max_search = d.max_search;
-  P.ncp = d.ncp; P.search = d.search; P.pad = 0;
+  P.ncp = d.ncp; P.search = d.search; P.eq = (int32_t)(d.eq_mask & 0xffu);
 }
 
 __device__ __forceinline__ int severity(int o) {
@@ -697,6 +697,7 @@ struct Sh1D {
   double tot[PGDTO_MAX_BLOCKS * 8];
   double red[NWAVE * BLOCK];
   double bs[PGDTO_MAX_BLOCKS];
+  double sg[PGDTO_MAX_BLOCKS];    // -1: an equality row searched in the opposite direction (lam < 0)
   double glob[8];
   Search S;
   PgdScalars pg;
@@ -722,6 +723,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   }
   for (int s = tid; s < d.nseg; s += BLOCK) {
     sh.bs[s] = d.b[s];
+    sh.sg[s] = 1.0;
     sh.S.state[s] = SEG_DONE; sh.S.lam[s] = 0.0; sh.S.npass[s] = 0; sh.S.width[s] = 0.0;
     sh.S.outcome[s] = PGDTO_INACTIVE; sh.S.scale[s] = 1.0; sh.S.ssat[s] = 0.0;
   }
@@ -845,150 +847,170 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       const TileGeom g = tile_geom<T>(d, tile);
       const int s = g.seg;
       if (ph == PH_ZERO) {
-        nv = 6; maxmask = 1ull << 2;
-        double acc[6] = {0, 0, -INFINITY, 0, 0, 0};
-        // lam = 0: a.clip(y), slope, largest breakpoint, saturated sum, sum |a|, non-finite count
-        auto zero_elem = [&](double y, double av) __attribute__((always_inline)) {
-          const double x0 = clampd(y, lo, hi);
-          acc[0] = fma(av, x0, acc[0]);
-          if (y >= lo && y <= hi) acc[1] = fma(av, av, acc[1]);
-          if (av != 0.0) {
-            const double bound = (av > 0.0) ? lo : hi;
-            acc[2] = fmax(acc[2], breakpoint(y, av, bound));
-            acc[3] = fma(av, bound, acc[3]);
-          }
-          acc[4] += fabs(av);
-          if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
-        };
-        if (tile == wid && g.nsweep <= RS) {
-          // load (pgd: form) this workgroup's first tile into registers
-          const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
-          {
-            int64_t re0[RS];
+        // rows held at equality (Sec. 3.2) also need the bracket of the
+        // opposite direction: a second instance of the pass adds its two sums
+        auto zero_tile = [&](auto eqc) __attribute__((always_inline)) {
+          constexpr bool EQ = decltype(eqc)::value;
+          constexpr int NZ = EQ ? 8 : 6;
+          nv = NZ;
+          maxmask = EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2);
+          // lam = 0: a.clip(y), slope, largest breakpoint, saturated sum, sum |a|,
+          // non-finite count [, largest opposite breakpoint, sum a . other bound]
+          double acc[NZ];
 #pragma unroll
-            for (int k = 0; k < RS; ++k) {
-              bool full; uint32_t mask;
-              rslot(g, k, re0[k], full, mask);
-              if (!mask) re0[k] = d.n;        // reads zeros
+          for (int v = 0; v < NZ; ++v) acc[v] = (v == 2 || v == 6) ? -INFINITY : 0.0;
+          // lam = 0: a.clip(y), slope, largest breakpoint, saturated sum, sum |a|, non-finite count
+          auto zero_elem = [&](double y, double av) __attribute__((always_inline)) {
+            const double x0 = clampd(y, lo, hi);
+            acc[0] = fma(av, x0, acc[0]);
+            if (y >= lo && y <= hi) acc[1] = fma(av, av, acc[1]);
+            if (av != 0.0) {
+              const double bound = (av > 0.0) ? lo : hi;
+              const double r = recip(av);
+              acc[2] = fmax(acc[2], (y - bound) * r);
+              acc[3] = fma(av, bound, acc[3]);
+              if constexpr (EQ) {
+                // the opposite direction (lam < 0) of an equality row: the
+                // element moves to the other bound
+                const double other = (av > 0.0) ? hi : lo;
+                acc[6] = fmax(acc[6], (other - y) * r);
+                acc[7] = fma(av, other, acc[7]);
+              }
+            }
+            acc[4] += fabs(av);
+            if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
+          };
+          if (tile == wid && g.nsweep <= RS) {
+            // load (pgd: form) this workgroup's first tile into registers
+            const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+            {
+              int64_t re0[RS];
+  #pragma unroll
+              for (int k = 0; k < RS; ++k) {
+                bool full; uint32_t mask;
+                rslot(g, k, re0[k], full, mask);
+                if (!mask) re0[k] = d.n;        // reads zeros
+              }
+              if (d.pgd) {
+                T tmp[RS][1][V];
+                const T* pa[1] = {A};
+                ld_slots<T, RS, 1>(pa, re0, d.n, tmp);
+  #pragma unroll
+                for (int k = 0; k < RS; ++k)
+  #pragma unroll
+                  for (int q = 0; q < V; ++q) ra[k][q] = tmp[k][0][q];
+              } else {
+                T tmp[RS][2][V];
+                const T* pa[2] = {A, Y};
+                ld_slots<T, RS, 2>(pa, re0, d.n, tmp);
+  #pragma unroll
+                for (int k = 0; k < RS; ++k)
+  #pragma unroll
+                  for (int q = 0; q < V; ++q) { ra[k][q] = tmp[k][0][q]; ry[k][q] = tmp[k][1][q]; }
+              }
             }
             if (d.pgd) {
-              T tmp[RS][1][V];
-              const T* pa[1] = {A};
-              ld_slots<T, RS, 1>(pa, re0, d.n, tmp);
-#pragma unroll
-              for (int k = 0; k < RS; ++k)
-#pragma unroll
-                for (int q = 0; q < V; ++q) ra[k][q] = tmp[k][0][q];
-            } else {
-              T tmp[RS][2][V];
-              const T* pa[2] = {A, Y};
-              ld_slots<T, RS, 2>(pa, re0, d.n, tmp);
-#pragma unroll
-              for (int k = 0; k < RS; ++k)
-#pragma unroll
-                for (int q = 0; q < V; ++q) { ra[k][q] = tmp[k][0][q]; ry[k][q] = tmp[k][1][q]; }
-            }
-          }
-          if (d.pgd) {
-            // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t
-            // in the stream precision; rho~ stays in registers.
-            // the loads of slot k + 1 are issued before d_t of slot k is
-            // stored (the store may alias them)
-            T nr[V], ng[V], nd[V];
-            auto fetch = [&](int k) __attribute__((always_inline)) {
-              int64_t e0 = d.n;               // reads zeros
-              if (k < RS) {
-                bool full; uint32_t mask;
+              // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t
+              // in the stream precision; rho~ stays in registers.
+              // the loads of slot k + 1 are issued before d_t of slot k is
+              // stored (the store may alias them)
+              T nr[V], ng[V], nd[V];
+              auto fetch = [&](int k) __attribute__((always_inline)) {
+                int64_t e0 = d.n;               // reads zeros
+                if (k < RS) {
+                  bool full; uint32_t mask;
+                  rslot(g, k, e0, full, mask);
+                  if (!mask) e0 = d.n;
+                }
+                T tmp[1][3][V];
+                const T* pa[3] = {(const T*)d.rho, (const T*)d.grad, d.zero_step ? (const T*)d.rho : (const T*)d.dir};
+                ld_slots<T, 1, 3>(pa, &e0, d.n, tmp);
+  #pragma unroll
+                for (int q = 0; q < V; ++q) {
+                  nr[q] = tmp[0][0][q];
+                  ng[q] = tmp[0][1][q];
+                  nd[q] = d.zero_step ? (T)0 : tmp[0][2][q];
+                }
+              };
+              fetch(0);
+  #pragma unroll
+              for (int k = 0; k < RS; ++k) {
+                T rr[V], rg[V], rd[V], dn[V];
+  #pragma unroll
+                for (int q = 0; q < V; ++q) { rr[q] = nr[q]; rg[q] = ng[q]; rd[q] = nd[q]; }
+                fetch(k + 1);
+                int64_t e0; bool full; uint32_t mask;
                 rslot(g, k, e0, full, mask);
-                if (!mask) e0 = d.n;
+                if (!mask) continue;
+  #pragma unroll
+                for (int q = 0; q < V; ++q) {
+                  const double dd = d.zero_step ? -f64(rg[q]) : fma(beta, f64(rd[q]), -f64(rg[q]));
+                  dn[q] = (T)dd;
+                  ry[k][q] = (T)fma(step, dd, f64(rr[q]));
+                }
+                st_vec<T>((T*)d.dir, e0, mask, full, dn);
               }
-              T tmp[1][3][V];
-              const T* pa[3] = {(const T*)d.rho, (const T*)d.grad, d.zero_step ? (const T*)d.rho : (const T*)d.dir};
-              ld_slots<T, 1, 3>(pa, &e0, d.n, tmp);
-#pragma unroll
-              for (int q = 0; q < V; ++q) {
-                nr[q] = tmp[0][0][q];
-                ng[q] = tmp[0][1][q];
-                nd[q] = d.zero_step ? (T)0 : tmp[0][2][q];
-              }
-            };
-            fetch(0);
-#pragma unroll
+            }
+            rbits = 0u;
+  #pragma unroll
             for (int k = 0; k < RS; ++k) {
-              T rr[V], rg[V], rd[V], dn[V];
-#pragma unroll
-              for (int q = 0; q < V; ++q) { rr[q] = nr[q]; rg[q] = ng[q]; rd[q] = nd[q]; }
-              fetch(k + 1);
               int64_t e0; bool full; uint32_t mask;
               rslot(g, k, e0, full, mask);
-              if (!mask) continue;
-#pragma unroll
+              rbits |= mask << (k * V);
+  #pragma unroll
               for (int q = 0; q < V; ++q) {
-                const double dd = d.zero_step ? -f64(rg[q]) : fma(beta, f64(rd[q]), -f64(rg[q]));
-                dn[q] = (T)dd;
-                ry[k][q] = (T)fma(step, dd, f64(rr[q]));
+                // elements outside the segment contribute exactly zero from here on
+                if (!(mask & (1u << q))) { ra[k][q] = (T)0; ry[k][q] = (T)0; }
+                else zero_elem(f64(ry[k][q]), f64(ra[k][q]));
               }
-              st_vec<T>((T*)d.dir, e0, mask, full, dn);
             }
-          }
-          rbits = 0u;
-#pragma unroll
-          for (int k = 0; k < RS; ++k) {
-            int64_t e0; bool full; uint32_t mask;
-            rslot(g, k, e0, full, mask);
-            rbits |= mask << (k * V);
-#pragma unroll
-            for (int q = 0; q < V; ++q) {
-              // elements outside the segment contribute exactly zero from here on
-              if (!(mask & (1u << q))) { ra[k][q] = (T)0; ry[k][q] = (T)0; }
-              else zero_elem(f64(ry[k][q]), f64(ra[k][q]));
+            resident = true;
+          } else if (d.pgd) {
+            // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t,
+            // materialized in the stream precision (it is the point projected).
+            T* Dw = (T*)d.dir;
+            const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
+            auto body = [&](const T* a, const T* r, const T* gr, const T* dp, int64_t e0, uint32_t mask, bool full)
+                __attribute__((always_inline)) {
+              T dn[V], rt[V];
+  #pragma unroll
+              for (int q = 0; q < V; ++q) {
+                const double dd = dp ? fma(beta, f64(dp[q]), -f64(gr[q])) : -f64(gr[q]);
+                dn[q] = (T)dd;
+                rt[q] = (T)fma(step, dd, f64(r[q]));
+              }
+              st_vec<T>(Dw, e0, mask, full, dn);
+              st_vec<T>(X, e0, mask, full, rt);
+  #pragma unroll
+              for (int q = 0; q < V; ++q)
+                if (mask & (1u << q)) zero_elem(f64(rt[q]), f64(a[q]));
+            };
+            if (d.zero_step) {
+              const T* ptr[3] = {A, (const T*)d.rho, (const T*)d.grad};
+              stream_tile<T, 3, SU1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+                body(b[0], b[1], b[2], nullptr, e0, mask, full);
+              });
+            } else {
+              const T* ptr[4] = {A, (const T*)d.rho, (const T*)d.grad, (const T*)d.dir};
+              stream_tile<T, 4, SU1>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+                body(b[0], b[1], b[2], b[3], e0, mask, full);
+              });
             }
-          }
-          resident = true;
-        } else if (d.pgd) {
-          // Alg. 3: d_t = -grad f + beta d_{t-1}; rho~ = rho_t + omega alpha_t d_t,
-          // materialized in the stream precision (it is the point projected).
-          T* Dw = (T*)d.dir;
-          const double beta = sh.pg.beta, step = d.omega * sh.pg.alpha;
-          auto body = [&](const T* a, const T* r, const T* gr, const T* dp, int64_t e0, uint32_t mask, bool full)
-              __attribute__((always_inline)) {
-            T dn[V], rt[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) {
-              const double dd = dp ? fma(beta, f64(dp[q]), -f64(gr[q])) : -f64(gr[q]);
-              dn[q] = (T)dd;
-              rt[q] = (T)fma(step, dd, f64(r[q]));
-            }
-            st_vec<T>(Dw, e0, mask, full, dn);
-            st_vec<T>(X, e0, mask, full, rt);
-#pragma unroll
-            for (int q = 0; q < V; ++q)
-              if (mask & (1u << q)) zero_elem(f64(rt[q]), f64(a[q]));
-          };
-          if (d.zero_step) {
-            const T* ptr[3] = {A, (const T*)d.rho, (const T*)d.grad};
-            stream_tile<T, 3, SU1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
-              body(b[0], b[1], b[2], nullptr, e0, mask, full);
-            });
           } else {
-            const T* ptr[4] = {A, (const T*)d.rho, (const T*)d.grad, (const T*)d.dir};
-            stream_tile<T, 4, SU1>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
-              body(b[0], b[1], b[2], b[3], e0, mask, full);
+            const T* ptr[2] = {Y, A};
+            stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+  #pragma unroll
+              for (int q = 0; q < V; ++q)
+                if (mask & (1u << q)) zero_elem(f64(b[0][q]), f64(b[1][q]));
             });
           }
-        } else {
-          const T* ptr[2] = {Y, A};
-          stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
-#pragma unroll
-            for (int q = 0; q < V; ++q)
-              if (mask & (1u << q)) zero_elem(f64(b[0][q]), f64(b[1][q]));
-          });
-        }
-        block_to_part<6>(acc, nv, maxmask, sh.red, pb, tile);
+          block_to_part<NZ>(acc, nv, maxmask, sh.red, pb, tile);
+        };
+        if (d.eq_mask) zero_tile(std::true_type{}); else zero_tile(std::false_type{});
       } else if (ph == PH_SEARCH) {
         nv = 2 * NT; maxmask = 0;
         if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
-        const double l0 = sh.S.trial[s][0], l1 = sh.S.trial[s][1];
+        const double l0 = sh.sg[s] * sh.S.trial[s][0], l1 = sh.sg[s] * sh.S.trial[s][1];
         // phi(lam_t) + b = a.clip(y - lam_t a) and its slope sum_free a^2, per trial;
         // elements outside the segment enter with a = 0, y = 0 and add nothing.
         // Two chains per sum (even and odd element of a vector), added at the
@@ -1037,7 +1059,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       } else {  // PH_FINAL
         nv = 4; maxmask = 0;
         double acc[4] = {0, 0, 0, 0};
-        const double lam = sh.S.lam[s];
+        const double lam = sh.sg[s] * sh.S.lam[s];
         const T* R = (const T*)d.rho;
         // x = clip(y - lam a) in the stream precision; a.x, free count, pgd norms
         auto final_slot = [&](const T* yv, const T* a, const T* r, int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) -> uint32_t {
@@ -1126,7 +1148,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
       }
     }
-    if (ph == PH_ZERO) { nv = 6; maxmask = 1ull << 2; }
+    if (ph == PH_ZERO) { nv = d.eq_mask ? 8 : 6; maxmask = d.eq_mask ? ((1ull << 2) | (1ull << 6)) : (1ull << 2); }
     else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
     else { nv = 4; maxmask = 0; }
 
@@ -1137,16 +1159,26 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 
     // ---------------- control (identical in every workgroup)
     if (ph == PH_ZERO) {
-      if (d.auto_tau > 0.0) kappa = auto_kappa(d.auto_tau, &sh.tot[2], 6, d.nseg);
+      const int zs = d.eq_mask ? 8 : 6;
+      if (d.auto_tau > 0.0) kappa = auto_kappa(d.auto_tau, &sh.tot[2], zs, d.nseg);
       for (int s = tid; s < d.nseg; s += BLOCK) {
-        const double* t = &sh.tot[s * 6];
+        const double* t = &sh.tot[s * zs];
         double scale = t[4] * fmax(fabs(lo), fabs(hi));
         if (!(scale > 0.0)) scale = 1.0;
+        const bool eq = (d.eq_mask >> s) & 1ull;
+        const double f0 = t[0] - sh.bs[s];
         if (t[5] > 0.0) {
           sh.S.lam[s] = 0.0; sh.S.outcome[s] = PGDTO_NONFINITE; sh.S.state[s] = SEG_DONE;
           sh.S.npass[s] = 0; sh.S.width[s] = 0.0; sh.S.scale[s] = scale;
+        } else if (eq && f0 < 0.0) {
+          // equality row below its target (Sec. 3.2): the opposite
+          // inequality (-a).x <= -b is the active one; search it for
+          // lam' >= 0 and report lam = -lam'
+          sh.sg[s] = -1.0;
+          search_init(sh.S, s, -f0, t[1] + kappa, t[6], -t[7], -sh.bs[s], kappa, scale, d.search, true);
         } else {
-          search_init(sh.S, s, t[0] - sh.bs[s], t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search, true);
+          search_init(sh.S, s, f0, t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search, true);
+          if (eq && sh.S.outcome[s] == PGDTO_INACTIVE) sh.S.outcome[s] = PGDTO_CONVERGED;   // h(0) = 0
         }
       }
       __syncthreads();
@@ -1159,8 +1191,9 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     } else if (ph == PH_SEARCH) {
       for (int s = tid; s < d.nseg; s += BLOCK) {
         if (sh.S.state[s] != SEG_SEARCH) continue;
-        search_update(sh.S, s, sh.tot[s * 4 + 0], sh.tot[s * 4 + 2], sh.tot[s * 4 + 1], sh.tot[s * 4 + 3],
-                      sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search, true);
+        const double sg = sh.sg[s];      // a sign-flipped row sees -a.x and -b
+        search_update(sh.S, s, sg * sh.tot[s * 4 + 0], sg * sh.tot[s * 4 + 2], sh.tot[s * 4 + 1],
+                      sh.tot[s * 4 + 3], sg * sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search, true);
       }
       __syncthreads();
       if (tid == 0) {
@@ -1173,9 +1206,9 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       if (wid == 0) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         for (int s = tid; s < d.nseg; s += BLOCK) {
-          R->lambda[s] = sh.S.lam[s];
+          R->lambda[s] = sh.sg[s] * sh.S.lam[s];
           R->resid[s] = sh.tot[s * 4 + 0] - sh.bs[s];
-          R->slack[s] = kappa * sh.S.lam[s];
+          R->slack[s] = kappa * sh.sg[s] * sh.S.lam[s];
           R->row_outcome[s] = sh.S.outcome[s];
         }
         if (tid == 0) {
@@ -1357,13 +1390,17 @@ __device__ __forceinline__ void unpack_J(const double* src, double* J) {
 
 // Continuous NCP: Phi_j = max(h_j, -c_j lam_j), c_j = J_jj + kappa, active if
 // h_j + c_j lam_j > 0.  Paper NCP (eq. phi): active if h_j > 0, Phi_j = h_j;
-// else Phi_j = -lam_j if h_j < 0, 0 if h_j = 0.
+// else Phi_j = -lam_j if h_j < 0, 0 if h_j = 0.  Equality rows (Sec. 3.2):
+// always active, Phi_j = h_j.
 template <int M>
 __device__ __forceinline__ void ncp(const double* h, const double* J, const double* lam, double kappa,
-                                    int mode, double* phi, bool* act) {
+                                    int mode, int eq, double* phi, bool* act) {
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    if (mode == PGDTO_NCP_PAPER) {
+    if ((eq >> j) & 1) {
+      act[j] = true;
+      phi[j] = h[j];
+    } else if (mode == PGDTO_NCP_PAPER) {
       act[j] = h[j] > 0.0;
       phi[j] = act[j] ? h[j] : (h[j] < 0.0 ? -lam[j] : 0.0);
     } else {
@@ -1438,11 +1475,11 @@ __device__ __forceinline__ void newton_direction(const double* h, const double* 
 // Scaled KKT residual of the current iterate (stopping rule): active rows
 // need |h_j| <= tol sigma_j, rows at lam_j = 0 need h_j <= tol sigma_j.
 template <int M>
-__device__ __forceinline__ double kkt_residual(const double* h, const double* lam, const double* scale) {
+__device__ __forceinline__ double kkt_residual(const double* h, const double* lam, const double* scale, int eq) {
   double r = 0.0;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    const double v = (lam[j] > 0.0) ? fabs(h[j]) : fmax(h[j], 0.0);
+    const double v = (((eq >> j) & 1) || lam[j] > 0.0) ? fabs(h[j]) : fmax(h[j], 0.0);
     r = fmax(r, v / scale[j]);
   }
   return r;
@@ -1471,7 +1508,8 @@ __device__ __forceinline__ int newton_accept(ShC& sh, const double (&lam)[M], co
 #pragma unroll
     for (int k = 0; k < M; ++k) N.J[j * PGDTO_MAX_M + k] = J[j * PGDTO_MAX_M + k];
   }
-  const double res = kkt_residual<M>(h, lam, scale);
+  const int eq = sh.P.eq;
+  const double res = kkt_residual<M>(h, lam, scale, eq);
   sh.res_inf = res;
   if (res <= tol_n || it >= max_newton) {
     sh.outcome = res <= tol_n ? PGDTO_CONVERGED : PGDTO_MAXITER;
@@ -1481,7 +1519,7 @@ __device__ __forceinline__ int newton_accept(ShC& sh, const double (&lam)[M], co
   }
   double phi[M], delta[M];
   bool act[M];
-  ncp<M>(h, J, lam, kappa, ncp_mode, phi, act);
+  ncp<M>(h, J, lam, kappa, ncp_mode, eq, phi, act);
   double p2 = 0.0;
 #pragma unroll
   for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
@@ -1495,7 +1533,7 @@ __device__ __forceinline__ int newton_accept(ShC& sh, const double (&lam)[M], co
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     N.delta[j] = delta[j];
-    N.trial[j] = fmax(lam[j] + delta[j], 0.0);
+    N.trial[j] = ((eq >> j) & 1) ? lam[j] + delta[j] : fmax(lam[j] + delta[j], 0.0);
   }
   return PH_NEWTON;
 }
@@ -1511,12 +1549,12 @@ __device__ __forceinline__ int newton_after_trial(ShC& sh, const double (&tr)[M]
 #pragma unroll
   for (int j = 0; j < M; ++j) { delta[j] = N.delta[j]; lam[j] = N.lam[j]; }
   const double kappa = sh.P.kappa, c1 = sh.P.c1, c2 = sh.P.c2;
-  const int ncp_mode = sh.P.ncp, max_ls = sh.P.max_ls;
+  const int ncp_mode = sh.P.ncp, max_ls = sh.P.max_ls, eq = sh.P.eq;
   const double M0 = N.M0, phi2 = N.phi2, gamma = N.gamma;
   const int have_best = N.have_best, ls = N.ls + 1;
   double phi[M];
   bool act[M];
-  ncp<M>(ht, Jt, tr, kappa, ncp_mode, phi, act);
+  ncp<M>(ht, Jt, tr, kappa, ncp_mode, eq, phi, act);
   double p2 = 0.0;
 #pragma unroll
   for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
@@ -1566,7 +1604,8 @@ __device__ __forceinline__ int newton_after_trial(ShC& sh, const double (&tr)[M]
   const double gnew = 0.5 * gamma;
   N.gamma = gnew;
 #pragma unroll
-  for (int j = 0; j < M; ++j) N.trial[j] = fmax(lam[j] + gnew * delta[j], 0.0);
+  for (int j = 0; j < M; ++j)
+    N.trial[j] = ((eq >> j) & 1) ? lam[j] + gnew * delta[j] : fmax(lam[j] + gnew * delta[j], 0.0);
   return PH_NEWTON;
 }
 
@@ -1932,7 +1971,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         sh.S.scale[j] = scale;
         sh.N.h0[j] = t[j] - sh.bs[j];
         sh.S.ssat[j] = t[3 * M + j];
-        if (d.stage1 && t[5 * M] == 0.0) {
+        if (d.stage1 && !d.eq_mask && t[5 * M] == 0.0) {
           search_init(sh.S, j, t[j] - sh.bs[j], t[M + j] + kappa, t[2 * M + j], t[3 * M + j], sh.bs[j], kappa,
                       scale, d.search, false);
         } else {
@@ -1942,8 +1981,8 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
       __syncthreads();
       if (tid == 0) {
         sh.passes += 1;
-        bool any_pos = false;
-        for (int j = 0; j < M; ++j) any_pos |= (sh.N.h0[j] > 0.0);
+        bool any_pos = false;     // some row needs a multiplier (equality rows: h(0) != 0)
+        for (int j = 0; j < M; ++j) any_pos |= ((d.eq_mask >> j) & 1) ? (sh.N.h0[j] != 0.0) : (sh.N.h0[j] > 0.0);
         if (t[5 * M] > 0.0) {
           sh.nonfinite = 1;
           sh.outcome = PGDTO_NONFINITE;
@@ -1952,7 +1991,9 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           sh.outcome = PGDTO_INACTIVE;
           sh.path = 0;
           sh.phase = PH_FINAL;
-        } else if (!d.stage1) {
+        } else if (!d.stage1 || d.eq_mask) {
+          // Stage 1 tests single active rows; equality rows are always
+          // active, so with any of them Newton starts at lam = 0
           sh.path = 3;
           for (int j = 0; j < M; ++j) sh.N.trial[j] = 0.0;
           sh.N.init = 1;

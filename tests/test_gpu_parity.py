@@ -228,6 +228,47 @@ def test_automatic_penalty(ctx, kind):
             assert r["resid"][j] <= tau * (1 + 1e-6) + 1e-6 * abs(p.b[j])
 
 
+def _eq_case(case):
+    if case.startswith("single"):
+        p = I.compliance_3d(4, n=50001)
+        if case == "single-raise":       # a.clip(y) below b: lam < 0 lifts the row to b
+            ax = float(p.A[0].astype(np.float64) @ np.clip(p.y.astype(np.float64), p.lo, p.hi))
+            p.b = np.array([ax + 0.3 * abs(ax)])
+        return p, [True]
+    if case == "independent":
+        p = I.multi_material(2, fields=4, n_per=30001)
+        p.b = p.b.copy()
+        p.b[0] = 0.7                     # above the field's mean: lifted
+        p.b[2] = 0.4
+        return p, [True, False, True, False]
+    p = I.volume_com(0, grid=(96, 48))
+    p.b = p.b.copy()
+    p.b[0] = 0.45 * float(np.sum(p.A[0]))   # volume held at 45%, above clip(y)'s
+    return p, [True, False, False, False, False]
+
+
+@pytest.mark.parametrize("case", ["single-lower", "single-raise", "independent", "coupled"])
+def test_equality_rows(ctx, case):
+    """Rows held at equality (Sec. 3.2): always active, multiplier of either
+    sign.  The HIP path against the oracle's equality solve."""
+    p, eq = _eq_case(case)
+    say("equality rows", case, p.n, eq)
+    y, A = dev(p.y), dev(p.A)
+    mask = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+    x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=mask, eq=eq)
+    torch.cuda.synchronize()
+    fm = free_from_mask(mask.cpu().numpy().view(np.uint32), p.n)
+    ref = oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets, eq=eq)
+    check(p, x.cpu().numpy(), r, ref, fm)
+    for j, e in enumerate(eq):
+        assert r["lam"][j] == pytest.approx(ref.lam[j], rel=1e-6, abs=1e-9 * max(1.0, abs(ref.lam[j]))), j
+        if e:
+            sig = P.row_scale(np.atleast_2d(p.dense_rows() if p.kind == "independent" else p.A), p.lo, p.hi)[j]
+            assert abs(r["resid"][j] - r["slack"][j]) <= 1e-6 * max(abs(p.b[j]), 1e-9 * sig)
+    if case in ("single-raise", "independent", "coupled"):
+        assert r["lam"][0] < 0.0
+
+
 def test_infeasible_single_row(ctx):
     rng = np.random.default_rng(12)
     n = 5000
