@@ -704,8 +704,11 @@ struct Sh1D {
   int32_t phase, abort_flag, passes, pad;
 };
 
-// SU: vector slots in flight per stream in the streaming passes.
-template <typename T, int SU = 2>
+// SU: vector slots in flight per stream in the streaming passes.  EQ: the
+// instance has rows held at equality (the zero pass adds the opposite
+// direction's bracket); a separate instantiation, so that the common case
+// keeps its register allocation.
+template <typename T, bool EQ = false, int SU = 2>
 __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   constexpr int V = VT<T>::N;
   constexpr int SU1 = SU > 2 ? SU / 2 : 1;     // for the 3- to 5-stream passes
@@ -848,9 +851,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       const int s = g.seg;
       if (ph == PH_ZERO) {
         // rows held at equality (Sec. 3.2) also need the bracket of the
-        // opposite direction: a second instance of the pass adds its two sums
-        auto zero_tile = [&](auto eqc) __attribute__((always_inline)) {
-          constexpr bool EQ = decltype(eqc)::value;
+        // opposite direction: the EQ instantiation adds its two sums
+        auto zero_tile = [&]() __attribute__((always_inline)) {
           constexpr int NZ = EQ ? 8 : 6;
           nv = NZ;
           maxmask = EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2);
@@ -1006,11 +1008,12 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           }
           block_to_part<NZ>(acc, nv, maxmask, sh.red, pb, tile);
         };
-        if (d.eq_mask) zero_tile(std::true_type{}); else zero_tile(std::false_type{});
+        zero_tile();
       } else if (ph == PH_SEARCH) {
         nv = 2 * NT; maxmask = 0;
         if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
-        const double l0 = sh.sg[s] * sh.S.trial[s][0], l1 = sh.sg[s] * sh.S.trial[s][1];
+        const double sgs = EQ ? sh.sg[s] : 1.0;
+        const double l0 = sgs * sh.S.trial[s][0], l1 = sgs * sh.S.trial[s][1];
         // phi(lam_t) + b = a.clip(y - lam_t a) and its slope sum_free a^2, per trial;
         // elements outside the segment enter with a = 0, y = 0 and add nothing.
         // Two chains per sum (even and odd element of a vector), added at the
@@ -1059,7 +1062,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       } else {  // PH_FINAL
         nv = 4; maxmask = 0;
         double acc[4] = {0, 0, 0, 0};
-        const double lam = sh.sg[s] * sh.S.lam[s];
+        const double lam = (EQ ? sh.sg[s] : 1.0) * sh.S.lam[s];
         const T* R = (const T*)d.rho;
         // x = clip(y - lam a) in the stream precision; a.x, free count, pgd norms
         auto final_slot = [&](const T* yv, const T* a, const T* r, int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) -> uint32_t {
@@ -1148,7 +1151,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
       }
     }
-    if (ph == PH_ZERO) { nv = d.eq_mask ? 8 : 6; maxmask = d.eq_mask ? ((1ull << 2) | (1ull << 6)) : (1ull << 2); }
+    if (ph == PH_ZERO) { nv = EQ ? 8 : 6; maxmask = EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2); }
     else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
     else { nv = 4; maxmask = 0; }
 
@@ -1159,13 +1162,13 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 
     // ---------------- control (identical in every workgroup)
     if (ph == PH_ZERO) {
-      const int zs = d.eq_mask ? 8 : 6;
+      constexpr int zs = EQ ? 8 : 6;
       if (d.auto_tau > 0.0) kappa = auto_kappa(d.auto_tau, &sh.tot[2], zs, d.nseg);
       for (int s = tid; s < d.nseg; s += BLOCK) {
         const double* t = &sh.tot[s * zs];
         double scale = t[4] * fmax(fabs(lo), fabs(hi));
         if (!(scale > 0.0)) scale = 1.0;
-        const bool eq = (d.eq_mask >> s) & 1ull;
+        const bool eq = EQ && ((d.eq_mask >> s) & 1ull);
         const double f0 = t[0] - sh.bs[s];
         if (t[5] > 0.0) {
           sh.S.lam[s] = 0.0; sh.S.outcome[s] = PGDTO_NONFINITE; sh.S.state[s] = SEG_DONE;
@@ -1175,7 +1178,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           // inequality (-a).x <= -b is the active one; search it for
           // lam' >= 0 and report lam = -lam'
           sh.sg[s] = -1.0;
-          search_init(sh.S, s, -f0, t[1] + kappa, t[6], -t[7], -sh.bs[s], kappa, scale, d.search, true);
+          if constexpr (EQ)
+            search_init(sh.S, s, -f0, t[1] + kappa, t[6], -t[7], -sh.bs[s], kappa, scale, d.search, true);
         } else {
           search_init(sh.S, s, f0, t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search, true);
           if (eq && sh.S.outcome[s] == PGDTO_INACTIVE) sh.S.outcome[s] = PGDTO_CONVERGED;   // h(0) = 0
@@ -1191,7 +1195,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     } else if (ph == PH_SEARCH) {
       for (int s = tid; s < d.nseg; s += BLOCK) {
         if (sh.S.state[s] != SEG_SEARCH) continue;
-        const double sg = sh.sg[s];      // a sign-flipped row sees -a.x and -b
+        const double sg = EQ ? sh.sg[s] : 1.0;      // a sign-flipped row sees -a.x and -b
         search_update(sh.S, s, sg * sh.tot[s * 4 + 0], sg * sh.tot[s * 4 + 2], sh.tot[s * 4 + 1],
                       sh.tot[s * 4 + 3], sg * sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search, true);
       }
@@ -1206,9 +1210,10 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       if (wid == 0) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         for (int s = tid; s < d.nseg; s += BLOCK) {
-          R->lambda[s] = sh.sg[s] * sh.S.lam[s];
+          const double lam_s = (EQ ? sh.sg[s] : 1.0) * sh.S.lam[s];
+          R->lambda[s] = lam_s;
           R->resid[s] = sh.tot[s * 4 + 0] - sh.bs[s];
-          R->slack[s] = kappa * sh.sg[s] * sh.S.lam[s];
+          R->slack[s] = kappa * lam_s;
           R->row_outcome[s] = sh.S.outcome[s];
         }
         if (tid == 0) {
@@ -1326,14 +1331,14 @@ __device__ __forceinline__ bool enter_launch(Desc& sd, int32_t* late_sh) {
   return *late_sh == 0;
 }
 
-template <typename T>
+template <typename T, bool EQ>
 __global__ __launch_bounds__(BLOCK, 2) void k_solve_1d(const Desc) {
   __shared__ Sh1D sh;
   __shared__ Desc sd;
   __shared__ int32_t late;
   load_desc(sd);
   if (!enter_launch(sd, &late)) return;
-  solve_1d<T>(sh, sd);
+  solve_1d<T, EQ>(sh, sd);
 }
 
 // ================================================================== coupled kernel
@@ -2168,7 +2173,8 @@ union ShSrv {
 __shared__ ShSrv srv_sh;
 __shared__ Desc srv_sd;
 
-__device__ __noinline__ void srv_solve_1d() { solve_1d<float>(srv_sh.s1, srv_sd); }
+template <bool EQ>
+__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ>(srv_sh.s1, srv_sd); }
 template <int M>
 __device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd); }
 
@@ -2275,8 +2281,10 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
         case 7: srv_solve_coupled<7>(); break;
         default: srv_solve_coupled<8>(); break;
       }
+    } else if (srv_sd.eq_mask) {
+      srv_solve_1d<true>();
     } else {
-      srv_solve_1d();
+      srv_solve_1d<false>();
     }
     __syncthreads();
     if (vb == 0 && threadIdx.x == 0) {
@@ -2311,14 +2319,16 @@ static const void* coupled_fn(int m) {
   }
 }
 
-static const void* kernel_fn(int kind, int dtype, int m) {
+static const void* kernel_fn(int kind, int dtype, int m, bool eq) {
   if (kind == PGDTO_COUPLED) return dtype == PGDTO_F32 ? coupled_fn<float>(m) : coupled_fn<double>(m);
-  return dtype == PGDTO_F32 ? (const void*)k_solve_1d<float> : (const void*)k_solve_1d<double>;
+  if (dtype == PGDTO_F32) return eq ? (const void*)k_solve_1d<float, true> : (const void*)k_solve_1d<float, false>;
+  return eq ? (const void*)k_solve_1d<double, true> : (const void*)k_solve_1d<double, false>;
 }
 
 int max_coresident(int kind, int dtype, int m, int device) {
   int nb = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_fn(kind, dtype, m), BLOCK, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_fn(kind, dtype, m, false), BLOCK, 0) != hipSuccess)
+    return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   return nb * ncu;
 }
@@ -2326,7 +2336,7 @@ int max_coresident(int kind, int dtype, int m, int device) {
 hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative) {
   Desc copy = d;
   void* args[] = {&copy};
-  const void* fn = kernel_fn(d.kind, d.dtype, d.m);
+  const void* fn = kernel_fn(d.kind, d.dtype, d.m, d.eq_mask != 0);
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
   return hipLaunchKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
 }

@@ -140,6 +140,43 @@ def test_server_matches_single_launch_bitwise(ctx, slots):
         assert r["lam"] == rs["lam"] and r["passes"] == rs["passes"], (r, rs)
 
 
+def test_server_equality_and_automatic_penalty_bitwise(ctx):
+    """Equality rows and the automatic penalty through a server slot give the
+    bits of a single launch."""
+    import dataclasses
+    from paper_2511_13905_amd.api import Batch, aligned_rows
+    p1 = I.compliance_3d(5, n=40001)
+    ax = float(p1.A[0].astype(np.float64) @ np.clip(p1.y.astype(np.float64), p1.lo, p1.hi))
+    p1.b = np.array([ax + 0.2 * abs(ax)])                    # equality row lifted to b
+    p2 = I.multi_material(4, fields=3, n_per=20011)
+    p3 = dataclasses.replace(I.volume_com(2, grid=(64, 32)), C=-1e-7)   # automatic penalty
+    cases = [(p1, [True]), (p2, [False, True, False]), (p3, None)]
+    say("server equality / automatic penalty", [p.n for p, _ in cases])
+    B = Batch(ctx, max_slots=4, slots_only=True)
+    staged = []
+    for p, eq in cases:
+        A = dev(p.A)
+        if p.kind != "independent":
+            A = aligned_rows(A)
+        staged.append((dev(p.y), A))
+    torch.cuda.synchronize()
+    tickets = [B.submit(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, eq=eq)
+               for (p, eq), (y, A) in zip(cases, staged)]
+    outs = []
+    for t in tickets:
+        x = B.x_of(t)
+        st, r, _ = B.wait(t)
+        torch.cuda.synchronize()
+        outs.append((st, r, x.cpu().numpy()))
+    B.close()
+    for (p, eq), (st, r, x) in zip(cases, outs):
+        assert st == 0
+        xs, rs = ctx.project(p.kind, dev(p.y), dev(p.A), p.b, p.lo, p.hi, p.C, offsets=p.offsets, eq=eq)
+        torch.cuda.synchronize()
+        assert np.array_equal(x, xs.cpu().numpy()), p.kind
+        assert r["lam"] == rs["lam"] and r["kappa"] == rs["kappa"], (r["lam"], rs["lam"])
+
+
 def test_server_alone_and_in_mix(ctx):
     """The same request gives the same bits alone and inside a busy mix."""
     from paper_2511_13905_amd.api import Batch
