@@ -53,11 +53,11 @@ def parse():
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
 MEASURED_TRAFFIC = {
     # profiles/k_solve_1d_f32_pgd_compliance_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "d1b628a4a1092e84", "bytes_per_launch": 214123440,
-                       "read": 180229816, "written": 33893624},
+    "pgd_compliance": {"kernel_sha": "c18acea01a40d8b9", "bytes_per_launch": 193739003,
+                       "read": 158817331, "written": 34921672},
     # profiles/k_solve_1d_f32_project_compliance_hbm_traffic.md
-    "project_compliance": {"kernel_sha": "d1b628a4a1092e84", "bytes_per_launch": 52116200,
-                           "read": 35098068, "written": 17018132},
+    "project_compliance": {"kernel_sha": "c18acea01a40d8b9", "bytes_per_launch": 54222946,
+                           "read": 36167002, "written": 18055944},
 }
 
 
@@ -329,6 +329,15 @@ def serve_bench(ctx, args):
     t, s, shape = _run_stream(ctx, structs, params, 0, zero)
     out["server_saturated"] = _stream_stats(t, s, ns)
     out["server_shape"] = {"slots": shape[0], "wg_per_slot": shape[1]}
+    # the throughput-oriented shape: the executor autotuner on the served mix
+    from paper_2511_13905_amd.api import batch_autotune
+    (ts, tw), cand = batch_autotune(
+        ctx, [(p.kind, y, A, p.b, p.lo, p.hi, p.C, p.offsets, x) for p, (y, A), x in zip(pool, dev, xs[:P])],
+        count=512, params=params)
+    t, s, shape = _run_stream(ctx, structs, params, ts, zero, tw)
+    out["server_saturated_tuned"] = _stream_stats(t, s, ns)
+    out["server_saturated_tuned"]["shape"] = {"slots": shape[0], "wg_per_slot": shape[1]}
+    out["server_saturated_tuned"]["autotune_wall_ms"] = dict(zip(["4", "8", "16", "32"], cand))
     r_plain = out["plain_saturated"]["requests_per_s"]
     for name, f in (("0.7x", 0.7), ("2x", 2.0)):
         rate = f * r_plain
