@@ -219,20 +219,27 @@ int pgdto_ctx_autotune(pgdto_ctx* ctx, int enable);
 /* Workgroups and tiles of the context's last launch. */
 int pgdto_ctx_last_launch(pgdto_ctx* ctx, int32_t* grid, int32_t* tiles);
 
-/* Project (Alg. 1 / Alg. 2).  Enqueues one cooperative launch on `stream`
- * and waits for it; *out is filled on return.  params may be NULL. */
+/* Project (Alg. 1 / Alg. 2).  Enqueues one launch on `stream` and waits
+ * for it; *out is filled on return.  params may be NULL. */
 int pgdto_project(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params,
                   pgdto_result* out, void* stream);
 
 /* Same, without waiting: the result struct is written to `result_dev`
  * (device memory, sizeof(pgdto_result) bytes, caller-owned) when the launch
  * completes in stream order.  Host arrays (b, block_offsets) are read before
- * the call returns. */
+ * the call returns.  The call enqueues exactly one kernel launch (no copy or
+ * memset), so it may be captured into a HIP graph: every replay runs as a
+ * new launch (the kernel takes its barrier epochs from a device-side
+ * counter of the context), with the b and offsets of the captured call.
+ * Launches on one context must not overlap in time (one stream, or ordered
+ * streams). */
 int pgdto_project_async(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params,
                         pgdto_result* result_dev, void* stream);
 
 /* One body of Algorithm 3 (step size, direction, rho~, projection, stop test),
- * one cooperative launch; waits and fills *out. */
+ * one launch; waits and fills *out.  The _async form writes the
+ * pgdto_pgd_out to device memory and, like pgdto_project_async, enqueues a
+ * single kernel launch that may be captured into a HIP graph and replayed. */
 int pgdto_pgd_step(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,
                    pgdto_pgd_out* out, void* stream);
 int pgdto_pgd_step_async(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,

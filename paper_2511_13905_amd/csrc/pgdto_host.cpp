@@ -287,7 +287,7 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   d.part = c->part;
   d.sync = c->sync;
   c->launch_seq += 1;
-  d.epoch0 = c->launch_seq << 20;
+  d.epoch0 = c->launch_seq << 20;   // replaced on the device by the door's generation
   d.trace = c->trace;
   d.result = result_dev;
   d.pgd = is_pgd ? 1 : 0;
@@ -295,9 +295,6 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   if (grid <= 0) return PGDTO_ERR_HIP;
   d.wg_base = 0;
   d.wg_count = grid;
-  if (d.free_mask) {
-    if (hipMemsetAsync(d.free_mask, 0, (size_t)((d.n + 31) / 32) * 4, s) != hipSuccess) return PGDTO_ERR_HIP;
-  }
   // an ordinary launch: the kernel's arrival door admits the workgroups that
   // are running together (normally all of them) and sends late ones home
   hipError_t e = launch_solve(d, grid, s, false);

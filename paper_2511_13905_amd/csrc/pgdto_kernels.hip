@@ -828,7 +828,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     uint32_t w = any ? (bits << (uint32_t)(e0 & 31)) : 0u;
 #pragma unroll
     for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
-    // the host zeroed the mask: only words with set bits are written
+    // the tile's mask words were zeroed at entry: only words with set bits are written
     if (w != 0u && ((tid & 63) % LPW) == 0) {
       const int64_t wi = e0 >> 5;
       const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
@@ -1263,18 +1263,33 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   report_error(d, errp);
 }
 
+// Zero the free-mask words of this workgroup's tiles (before the first grid
+// barrier; the final pass sets bits only where elements are free).
+template <typename T>
+__device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
+  if (!d.free_mask) return;
+  const int wid = wg_id(d), G = wg_num(d);
+  for (int tile = wid; tile < d.ntiles; tile += G) {
+    const TileGeom g = tile_geom<T>(d, tile);
+    const int64_t w0 = g.ts >> 5, w1 = (g.te + 31) >> 5;
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += BLOCK) d.free_mask[w] = 0u;
+  }
+}
+
 // ------------------------------------------------------------------ arrival door
 // One-instance launches are ordinary launches (a cooperative launch costs the
 // runtime about 17 us more per launch), so that all of the grid is resident
 // is not guaranteed; the grid barrier needs every participant running.  Each
 // workgroup therefore takes a ticket at entry with one atomic add on the
-// launch's door word.  The first arrival waits (bounded) until the whole grid
-// has arrived, closes the door and publishes the count; a workgroup arriving
-// after that leaves at once, and the participants take their ticket as
-// workgroup id.  Results do not depend on the count (tile-ordered
-// reductions).  The door word carries the launch's tag (from epoch0, unique
-// per launch of a context) in its upper half, so no reset between launches is
-// needed: the first arrivals of a launch replace a stale word.
+// context's door word, [generation:32 | closed:1 | count:31].  The first
+// arrival waits (bounded) until the whole grid has arrived, closes the door
+// and publishes the count; a workgroup arriving after that leaves at once,
+// and the participants take their ticket as workgroup id.  Results do not
+// depend on the count (tile-ordered reductions).  The last of the grid's
+// arrivals (the first one when nobody came late) reopens the door with the
+// next generation, and the generation also gives the launch's barrier epochs:
+// nothing the host wrote for this launch has to be unique, so a replayed
+// graph of launches works as the launches did.
 constexpr uint64_t DOOR_CLOSED = 1ull << 31;
 constexpr uint64_t DOOR_COUNT = DOOR_CLOSED - 1;
 constexpr uint64_t DOOR_WAIT_TICKS = 3000;     // 30 us on the 100 MHz clock
@@ -1287,43 +1302,45 @@ __device__ __forceinline__ uint64_t* door_words(const Desc& d) {
 __device__ __forceinline__ bool enter_launch(Desc& sd, int32_t* late_sh) {
   if (threadIdx.x == 0) {
     uint64_t* door = door_words(sd);
-    uint64_t* pub = door + FLAG_STRIDE;
-    const uint64_t tag = (sd.epoch0 >> 20) & 0xffffffffull;
-    uint64_t cur = __hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // a stale word changes only when a workgroup of this launch opens it:
-    // at most two rounds
-    while ((cur >> 32) != tag) {
-      if (__hip_atomic_compare_exchange_strong(door, &cur, tag << 32, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT))
-        break;
-    }
+    uint64_t* pub = door + FLAG_STRIDE;      // [generation + 1 : 32 | count : 32]
+    const uint64_t G = gridDim.x;
     const uint64_t old = __hip_atomic_fetch_add(door, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t gen = old >> 32;
+    const uint64_t next_open = (gen + 1) << 32;
     int late = (old & DOOR_CLOSED) != 0;
-    const int ticket = (int)(old & DOOR_COUNT);
-    int count = 0;
-    if (!late && ticket == 0) {
+    const uint64_t ticket = old & DOOR_COUNT;
+    uint64_t count = 0;
+    if (late) {
+      if (ticket == G - 1)                   // the grid's last arrival: reopen for the next launch
+        __hip_atomic_store(door, next_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (ticket == 0) {
       const uint64_t t0 = clk();
-      while ((__hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DOOR_COUNT) < gridDim.x &&
+      while ((__hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DOOR_COUNT) < G &&
              clk() - t0 < DOOR_WAIT_TICKS)
         __builtin_amdgcn_s_sleep(1);
       const uint64_t fin = __hip_atomic_fetch_or(door, DOOR_CLOSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      count = (int)(fin & DOOR_COUNT);
-      __hip_atomic_store(pub, (tag << 32) | (uint64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (!late) {
+      count = fin & DOOR_COUNT;
+      // the whole grid is in: no one else touches this launch's door
+      if (count == G) __hip_atomic_store(door, next_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(pub, ((gen + 1) << 32) | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
       // the first arrival is running and publishes within the wait above;
       // the spin cap only guards against the impossible
       uint64_t v = 0;
       uint32_t spins = 0;
-      while (((v = __hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
+      while (((v = __hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != gen + 1) {
         __builtin_amdgcn_s_sleep(1);
         if (++spins > SPIN_LIMIT) break;
       }
-      if ((v >> 32) == tag) count = (int)(v & 0xffffffffull);
+      if ((v >> 32) == gen + 1) count = v & 0xffffffffull;
       else late = 1;
     }
     if (!late) {
-      sd.wg_base = (int32_t)blockIdx.x - ticket;
-      sd.wg_count = count;
+      sd.wg_base = (int32_t)blockIdx.x - (int32_t)ticket;
+      sd.wg_count = (int32_t)count;
+      // barrier epochs of this launch: above every flag an earlier launch of
+      // this context left (generations grow by one per launch)
+      sd.epoch0 = (gen + 1) << 20;
     }
     *late_sh = late;
   }
@@ -1338,6 +1355,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_solve_1d(const Desc) {
   __shared__ int32_t late;
   load_desc(sd);
   if (!enter_launch(sd, &late)) return;
+  clear_mask_tiles<T>(sd);
   solve_1d<T, EQ>(sh, sd);
 }
 
@@ -1937,7 +1955,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
             uint32_t w = any ? (bits << (uint32_t)(e0 & 31)) : 0u;
 #pragma unroll
             for (int o = 1; o < LPW; o <<= 1) w |= (uint32_t)__shfl_xor((int)w, o, 64);
-            // the host zeroed the mask: only words with set bits are written
+            // the tile's mask words were zeroed at entry: only words with set bits are written
             if (w != 0u && (lane % LPW) == 0) {
               const int64_t wi = e0 >> 5;
               const bool whole = (wi * 32 >= g.sstart) && (wi * 32 + 32 <= g.te);
@@ -2143,6 +2161,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve_coupled(const Desc) {
   __shared__ int32_t late;
   load_desc(sd);
   if (!enter_launch(sd, &late)) return;
+  clear_mask_tiles<T>(sd);
   solve_coupled<T, M>(sh, sd);
 }
 
@@ -2178,16 +2197,6 @@ __device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ>(srv_sh.s1, srv
 template <int M>
 __device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd); }
 
-template <typename T>
-__device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
-  if (!d.free_mask) return;
-  const int wid = wg_id(d), G = wg_num(d);
-  for (int tile = wid; tile < d.ntiles; tile += G) {
-    const TileGeom g = tile_geom<T>(d, tile);
-    const int64_t w0 = g.ts >> 5, w1 = (g.te + 31) >> 5;
-    for (int64_t w = w0 + threadIdx.x; w < w1; w += BLOCK) d.free_mask[w] = 0u;
-  }
-}
 
 __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
   __shared__ SrvArgs a;

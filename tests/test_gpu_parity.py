@@ -269,6 +269,57 @@ def test_equality_rows(ctx, case):
         assert r["lam"][0] < 0.0
 
 
+def test_graph_replay_matches_eager(ctx):
+    """One-instance launches captured in a HIP graph (two projections, masks
+    included) and replayed three times, with eager launches on the same
+    context between replays: every replay gives the bits of eager calls."""
+    from paper_2511_13905_amd.api import result_from_bytes, result_nbytes
+    probs = [I.compliance_3d(6, n=100003), I.volume_com(1, grid=(64, 32))]
+    say("graph replay", [p.n for p in probs])
+    dev_in = [(dev(p.y), dev(p.A)) for p in probs]
+    xs = [torch.empty(p.n, dtype=torch.float32, device="cuda:0") for p in probs]
+    ms = [torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0") for p in probs]
+    rs = [torch.zeros(result_nbytes(), dtype=torch.uint8, device="cuda:0") for _ in probs]
+
+    def enqueue():
+        for p, (y, A), x, m, r in zip(probs, dev_in, xs, ms, rs):
+            ctx.project_async(p.kind, y, A, p.b, p.lo, p.hi, r, C=p.C, offsets=p.offsets, x=x, free_mask=m)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        enqueue()                                    # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        enqueue()
+    torch.cuda.synchronize()
+    eager = []
+    for p, (y, A) in zip(probs, dev_in):
+        m = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+        x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=m)
+        torch.cuda.synchronize()
+        eager.append((x.cpu().numpy(), m.cpu().numpy(), r))
+    other = I.multi_material(5, fields=2, n_per=20011)
+    for rep in range(3):
+        for x, m in zip(xs, ms):
+            x.fill_(-1.0)
+            m.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (xe, me, re_), x, m, r in zip(eager, xs, ms, rs):
+            assert np.array_equal(x.cpu().numpy(), xe), rep
+            assert np.array_equal(m.cpu().numpy(), me), rep
+            rr = result_from_bytes(r)
+            assert rr["lam"] == re_["lam"] and rr["passes"] == re_["passes"] and rr["error"] == 0, (rep, rr, re_)
+        # an eager launch on the same context between replays
+        ctx.project(other.kind, dev(other.y), dev(other.A), other.b, other.lo, other.hi, other.C,
+                    offsets=other.offsets)
+        torch.cuda.synchronize()
+
+
 def test_infeasible_single_row(ctx):
     rng = np.random.default_rng(12)
     n = 5000
