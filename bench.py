@@ -53,11 +53,11 @@ def parse():
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
 MEASURED_TRAFFIC = {
     # profiles/k_solve_1d_f32_pgd_compliance_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "c18acea01a40d8b9", "bytes_per_launch": 193739003,
-                       "read": 158817331, "written": 34921672},
+    "pgd_compliance": {"kernel_sha": "985708f118d20d61", "bytes_per_launch": 193652904,
+                       "read": 158750928, "written": 34901976},
     # profiles/k_solve_1d_f32_project_compliance_hbm_traffic.md
-    "project_compliance": {"kernel_sha": "c18acea01a40d8b9", "bytes_per_launch": 54222946,
-                           "read": 36167002, "written": 18055944},
+    "project_compliance": {"kernel_sha": "985708f118d20d61", "bytes_per_launch": 54132394,
+                           "read": 36097182, "written": 18035212},
 }
 
 
