@@ -116,6 +116,11 @@ extern "C" int pgdto_ctx_create(int device, pgdto_ctx** out) {
     // size of a server slot, to study a slot's passes in isolation)
     const char* gv = getenv("PGDTO_GRID");
     if (gv && gv[0]) c->forced_grid = std::max(0, atoi(gv));
+    // PGDTO_DOOR_WAIT=t: the arrival door of one-instance launches waits at
+    // most t ticks of the 100 MHz clock for the grid (default 3000 = 30 us;
+    // 0 closes it at the first arrival, so that late workgroups occur)
+    const char* dv = getenv("PGDTO_DOOR_WAIT");
+    if (dv && dv[0]) c->door_wait = (uint64_t)std::max(0LL, atoll(dv));
   }
   {
     const char* tv = getenv("PGDTO_TRACE");
@@ -295,6 +300,7 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   if (grid <= 0) return PGDTO_ERR_HIP;
   d.wg_base = 0;
   d.wg_count = grid;
+  d.door_wait = c->door_wait;
   // an ordinary launch: the kernel's arrival door admits the workgroups that
   // are running together (normally all of them) and sends late ones home
   hipError_t e = launch_solve(d, grid, s, false);

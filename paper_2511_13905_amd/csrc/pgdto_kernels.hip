@@ -1124,8 +1124,13 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           T ny[V], na[V], nr[V];
           int64_t ne0 = 0; bool nfull = false, nany = false; uint32_t nmask = 0u;
           auto fetch = [&](int k) __attribute__((always_inline)) {
+            // a slot with no element of this segment keeps its own position:
+            // put_mask addresses the word of 8 lanes by the first lane's
+            // position, and at a block start that lane may hold only
+            // elements of the previous block
+            ne0 = 0;
             nany = (k < g.nsweep) && slot<T>(g, k, ne0, nfull, nmask);
-            if (!nany) { nmask = 0u; ne0 = 0; nfull = false; }
+            if (!nany) { nmask = 0u; nfull = false; }
             int64_t le0 = nany ? ne0 : d.n;    // reads zeros
             T tmp[1][3][V];
             const T* pa[3] = {Y, A, d.pgd ? R : Y};
@@ -1282,7 +1287,8 @@ __device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
 // is not guaranteed; the grid barrier needs every participant running.  Each
 // workgroup therefore takes a ticket at entry with one atomic add on the
 // context's door word, [generation:32 | closed:1 | count:31].  The first
-// arrival waits (bounded) until the whole grid has arrived, closes the door
+// arrival waits (bounded: Desc::door_wait, 30 us by default) until the whole
+// grid has arrived, closes the door
 // and publishes the count; a workgroup arriving after that leaves at once,
 // and the participants take their ticket as workgroup id.  Results do not
 // depend on the count (tile-ordered reductions).  The last of the grid's
@@ -1292,7 +1298,6 @@ __device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
 // graph of launches works as the launches did.
 constexpr uint64_t DOOR_CLOSED = 1ull << 31;
 constexpr uint64_t DOOR_COUNT = DOOR_CLOSED - 1;
-constexpr uint64_t DOOR_WAIT_TICKS = 3000;     // 30 us on the 100 MHz clock
 
 __device__ __forceinline__ uint64_t* door_words(const Desc& d) {
   return d.sync + (size_t)GMAX * FLAG_STRIDE + (size_t)NREP * REP_WORDS + FLAG_STRIDE + TOT_MAX;
@@ -1316,7 +1321,7 @@ __device__ __forceinline__ bool enter_launch(Desc& sd, int32_t* late_sh) {
     } else if (ticket == 0) {
       const uint64_t t0 = clk();
       while ((__hip_atomic_load(door, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & DOOR_COUNT) < G &&
-             clk() - t0 < DOOR_WAIT_TICKS)
+             clk() - t0 < sd.door_wait)
         __builtin_amdgcn_s_sleep(1);
       const uint64_t fin = __hip_atomic_fetch_or(door, DOOR_CLOSED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       count = fin & DOOR_COUNT;

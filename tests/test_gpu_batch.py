@@ -177,6 +177,26 @@ def test_server_equality_and_automatic_penalty_bitwise(ctx):
         assert r["lam"] == rs["lam"] and r["kappa"] == rs["kappa"], (r["lam"], rs["lam"])
 
 
+def test_server_small_slots_stream_block_starts(ctx):
+    """Independent blocks on slots of 2 workgroups: most tiles are streamed
+    (not held in registers), including the tiles that open a block at an
+    unaligned element; masks and x are the bits of a single launch."""
+    from paper_2511_13905_amd.api import Batch
+    reqs = [I.multi_material(6, fields=3, n_per=40011), I.multi_material(8, fields=4, n_per=25013)]
+    say("server small slots", [p.n for p in reqs])
+    st_in = stage(reqs)
+    B = Batch(ctx, max_slots=8, wg_per_slot=2, slots_only=True)
+    handles = [submit(B, p, s) for p, s in zip(reqs, st_in)]
+    outs = [collect(B, t, fm, p.n) for (t, fm), p in zip(handles, reqs)]
+    B.close()
+    for p, (st, r, x, mask, _) in zip(reqs, outs):
+        assert st == 0
+        xs, rs, ms = single(ctx, p)
+        assert np.array_equal(x, xs)
+        assert np.array_equal(mask, ms)
+        assert r["lam"] == rs["lam"]
+
+
 def test_server_alone_and_in_mix(ctx):
     """The same request gives the same bits alone and inside a busy mix."""
     from paper_2511_13905_amd.api import Batch

@@ -320,6 +320,49 @@ def test_graph_replay_matches_eager(ctx):
         torch.cuda.synchronize()
 
 
+def test_late_arrivals_give_the_same_bits(ctx):
+    """An arrival door that closes at the first arrival (PGDTO_DOOR_WAIT=0)
+    leaves most of the grid out: the participants solve every tile, late
+    workgroups leave, the last of them reopens the door.  Several launches in
+    a row of every kind give the bits of full-grid launches."""
+    import os
+    from paper_2511_13905_amd.api import Context
+    os.environ["PGDTO_DOOR_WAIT"] = "0"
+    try:
+        c0 = Context(0)
+    finally:
+        del os.environ["PGDTO_DOOR_WAIT"]
+    probs = [I.compliance_3d(7, n=200003), I.multi_material(6, fields=3, n_per=40011),
+             I.volume_com(0, grid=(64, 32)), I.volume_com(1, grid=(48, 24))]
+    say("late arrivals", [p.n for p in probs])
+    st = I.pgd_compliance_3d(2, t=60, n=150001)
+    try:
+        for rep in range(2):
+            for p in probs:
+                outs = []
+                for c in (c0, ctx):
+                    m = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+                    x, r = c.project(p.kind, dev(p.y), dev(p.A), p.b, p.lo, p.hi, p.C, offsets=p.offsets,
+                                     free_mask=m)
+                    torch.cuda.synchronize()
+                    outs.append((x.cpu().numpy(), m.cpu().numpy(), r))
+                (x0, m0, r0), (x1, m1, r1) = outs
+                assert r0["error"] == 0 and r1["error"] == 0
+                assert np.array_equal(x0, x1) and np.array_equal(m0, m1), (rep, p.kind)
+                assert r0["lam"] == r1["lam"] and r0["passes"] == r1["passes"]
+            pg = []
+            for c in (c0, ctx):
+                d = dev(st.d_prev)
+                x, out = c.pgd_step("single", dev(st.problem.A), dev(st.rho), dev(st.rho_prev), dev(st.grad),
+                                    dev(st.grad_prev), d, st.g, st.G, st.t, I.LO, I.HI)
+                torch.cuda.synchronize()
+                pg.append((x.cpu().numpy(), d.cpu().numpy(), out))
+            assert np.array_equal(pg[0][0], pg[1][0]) and np.array_equal(pg[0][1], pg[1][1])
+            assert pg[0][2]["alpha"] == pg[1][2]["alpha"] and pg[0][2]["proj"]["lam"] == pg[1][2]["proj"]["lam"]
+    finally:
+        c0.close()
+
+
 def test_infeasible_single_row(ctx):
     rng = np.random.default_rng(12)
     n = 5000
