@@ -332,18 +332,22 @@ def test_late_arrivals_give_the_same_bits(ctx):
         c0 = Context(0)
     finally:
         del os.environ["PGDTO_DOOR_WAIT"]
+    p64 = I.compliance_3d(8, n=90001)
+    p64.y = p64.y.astype(np.float64)
+    p64.A = p64.A.astype(np.float64)
     probs = [I.compliance_3d(7, n=200003), I.multi_material(6, fields=3, n_per=40011),
-             I.volume_com(0, grid=(64, 32)), I.volume_com(1, grid=(48, 24))]
+             I.volume_com(0, grid=(64, 32)), I.volume_com(1, grid=(48, 24)), p64]
+    eqs = [None, [True, False, True], [True, False, False, False, False], None, None]
     say("late arrivals", [p.n for p in probs])
     st = I.pgd_compliance_3d(2, t=60, n=150001)
     try:
         for rep in range(2):
-            for p in probs:
+            for p, eq in zip(probs, eqs):
                 outs = []
                 for c in (c0, ctx):
                     m = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
                     x, r = c.project(p.kind, dev(p.y), dev(p.A), p.b, p.lo, p.hi, p.C, offsets=p.offsets,
-                                     free_mask=m)
+                                     free_mask=m, eq=(eq if rep == 1 else None))
                     torch.cuda.synchronize()
                     outs.append((x.cpu().numpy(), m.cpu().numpy(), r))
                 (x0, m0, r0), (x1, m1, r1) = outs
