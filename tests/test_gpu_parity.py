@@ -451,6 +451,39 @@ def test_pgd_step_single(ctx, t, rule):
     assert out["rel_change"] == pytest.approx(ref["rel_change"], rel=1e-5)
 
 
+@pytest.mark.parametrize("t", [0, 70])
+def test_pgd_step_independent(ctx, t):
+    """Algorithm 3 on independent blocks (three material fields, one volume
+    cap each): b_j = G_j - g_j + a_j.rho_t per block."""
+    rng = np.random.default_rng(9 + t)
+    n_per, m = 40011, 3
+    n = n_per * m
+    offsets = np.arange(m + 1, dtype=np.int64) * n_per
+    A = np.full(n, 1.0 / n_per, dtype=np.float32)
+    rho = np.clip(rng.uniform(0, 0.6, n), I.LO, I.HI).astype(np.float32)
+    grad = rng.standard_normal(n).astype(np.float32)
+    rho_prev = (rho - 0.01 * rng.standard_normal(n)).astype(np.float32)
+    grad_prev = (grad + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    d_prev = (-grad_prev).astype(np.float32)
+    A64 = A.astype(np.float64)
+    g = np.array([float(A64[offsets[j]:offsets[j + 1]] @ rho[offsets[j]:offsets[j + 1]].astype(np.float64))
+                  for j in range(m)])
+    G = np.array([0.25, 0.3, 0.2])
+    say("pgd_step independent", t, n)
+    d = dev(d_prev)
+    x, out = ctx.pgd_step("independent", dev(A), dev(rho), dev(rho_prev), dev(grad), dev(grad_prev), d, g, G, t,
+                          I.LO, I.HI, offsets=offsets)
+    torch.cuda.synchronize()
+    ref = oracle.pgd_step("independent", rho, rho_prev, grad, grad_prev, d_prev, A, g, G, t, I.LO, I.HI,
+                          offsets=offsets, stream_dtype=np.float32)
+    assert out["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+    assert out["used_fallback"] == ref["used_fallback"]
+    np.testing.assert_allclose(d.cpu().numpy(), ref["d"], rtol=1e-6, atol=1e-7)
+    prob = I.Problem("independent", ref["rho_tilde"], A, ref["b"], offsets=offsets)
+    check(prob, x.cpu().numpy(), out["proj"], ref["proj"])
+    assert out["rel_change"] == pytest.approx(ref["rel_change"], rel=1e-5)
+
+
 def test_pgd_step_coupled(ctx):
     p = I.volume_com(0, grid=(32, 16, 16))
     rng = np.random.default_rng(5)
