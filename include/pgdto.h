@@ -216,6 +216,14 @@ int pgdto_ctx_destroy(pgdto_ctx* ctx);
  * forget.  Results do not depend on the choice (bitwise).  Returns the
  * previous setting or PGDTO_ERR_ARG. */
 int pgdto_ctx_autotune(pgdto_ctx* ctx, int enable);
+/* Two more environment variables read at context creation, for studies of
+ * the launch (results do not depend on either, bitwise):
+ *   PGDTO_GRID=k       one-instance launches use at most k workgroups (the
+ *                      size of a server slot, traced in isolation);
+ *   PGDTO_DOOR_WAIT=t  the kernel's arrival door waits at most t ticks of the
+ *                      100 MHz clock for the whole grid before it closes
+ *                      (default 3000 = 30 us; 0 closes it at the first
+ *                      arrival, so that fewer workgroups take part). */
 /* Workgroups and tiles of the context's last launch. */
 int pgdto_ctx_last_launch(pgdto_ctx* ctx, int32_t* grid, int32_t* tiles);
 
