@@ -236,7 +236,8 @@ def main():
         line["serving"] = serve_bench(ctx, args)
         line["batched"] = batched_bench(ctx)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, insts, args.cpu_seconds, n)
+        line["cpu_baseline"], refs = cpu_baseline(wl, insts, args.cpu_seconds, n)
+        line["oracle_error"] = oracle_error(ctx, wl, insts, refs)
     ctx.close()
     print(json.dumps(line), flush=True)
 
@@ -422,20 +423,60 @@ def cpu_baseline(wl, insts, budget_s, n):
     import oracle
     from paper_2511_13905_amd import inputs as I
     done = 0
+    refs = []
     t0 = time.perf_counter()
     while done < len(insts) and time.perf_counter() - t0 < budget_s:
         it = insts[done]
         if wl == "pgd_compliance":
             st = it["st"]
-            oracle.pgd_step("single", st.rho, st.rho_prev, st.grad, st.grad_prev, st.d_prev, st.problem.A,
-                            st.g, st.G, st.t, I.LO, I.HI, stream_dtype=np.float32)
+            refs.append(oracle.pgd_step("single", st.rho, st.rho_prev, st.grad, st.grad_prev, st.d_prev,
+                                        st.problem.A, st.g, st.G, st.t, I.LO, I.HI, stream_dtype=np.float32))
         else:
             p = it["p"]
-            oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets)
+            refs.append(oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets))
         done += 1
     el = time.perf_counter() - t0
-    return {"value": done * n / el, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} full-size instance(s) of the same workload in {el:.1f} s (numpy float64, one thread)"}
+    return ({"value": done * n / el, "unit": "elements/s", "cores": 1, "kind": "oracle",
+             "sample": f"{done} full-size instance(s) of the same workload in {el:.1f} s (numpy float64, one thread)"},
+            refs)
+
+
+def oracle_error(ctx, wl, insts, refs):
+    """Error of the GPU result against the float64 oracle on the instances the
+    CPU baseline solved (each solved once more on the GPU from its original
+    inputs, outside the timed region): x relative to |x|, the constraint
+    residual relative to |b_j| (to the row scale sigma_j = sum |a_j| max(|lo|,
+    |hi|) where b_j is zero up to rounding, as in the parity tests), the
+    multiplier relative to itself."""
+    import numpy as np
+    import torch
+    from paper_2511_13905_amd import inputs as I
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    xe, re_, le = 0.0, 0.0, 0.0
+    for it, ref in zip(insts, refs):
+        if wl == "pgd_compliance":
+            st = it["st"]
+            x, out = ctx.pgd_step("single", it["A"], it["rho"], it["rho_prev"], it["grad"], it["grad_prev"],
+                                  dev(st.d_prev), st.g, st.G, st.t, I.LO, I.HI)
+            r, o, b = out["proj"], ref["proj"], ref["b"]
+            rows = np.atleast_2d(st.problem.A).astype(np.float64)
+        else:
+            p = it["p"]
+            x, r = ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C, offsets=p.offsets)
+            o, b = ref, p.b
+            rows = p.dense_rows()
+        sig = np.abs(rows).sum(axis=1) * max(abs(I.LO), abs(I.HI))
+        torch.cuda.synchronize()
+        xv = x.cpu().numpy().astype(np.float64)
+        xe = max(xe, float(np.max(np.abs(xv - o.x) / np.maximum(np.abs(o.x), 1e-300))))
+        for j in range(len(o.resid)):
+            bj = abs(float(b[j]))
+            scale = bj if bj > 1e-9 * sig[j] else sig[j]
+            re_ = max(re_, abs(r["resid"][j] - o.resid[j]) / max(scale, 1e-300))
+            if o.lam[j] != 0.0:
+                le = max(le, abs(r["lam"][j] - o.lam[j]) / abs(o.lam[j]))
+    return {"instances": len(refs), "x_rel_max": xe, "resid_rel_max": re_, "lam_rel_max": le,
+            "tolerance": {"x_rel": 1e-5, "resid_rel": 1e-6}}
 
 
 if __name__ == "__main__":
