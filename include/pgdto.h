@@ -15,6 +15,9 @@
  * x = clip(y - A^T lam, lo, hi) for the unique multiplier lam >= 0 (lam is the
  * paper's -y) with h(lam) <= 0 and lam_j h_j(lam) = 0, where
  * h_j(lam) = a_j.x(lam) - b_j - kappa lam_j (Appendix A.2, eq. (h)).
+ * Rows flagged in pgdto_problem.eq_mask are equalities a_j.x = b_j (Sec. 3.2,
+ * the note on equality constraints): always active, lam_j of either sign.
+ * A negative C asks for the automatic penalty of Appendix A.2.
  *
  *   PGDTO_SINGLE       one dense row: Algorithm 1 (dual bracket search).
  *   PGDTO_INDEPENDENT  m rows on disjoint contiguous element ranges
@@ -54,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 1
+#define PGDTO_VERSION 2      /* 2: eq_mask, automatic C, pgdto_result.kappa */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
