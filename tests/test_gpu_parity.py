@@ -146,6 +146,16 @@ def test_volume_com_small(ctx, seed):
     print(r["path"], r["passes"], r["iters_newton"], flush=True)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_volume_com_f64(ctx, seed):
+    """The coupled kernel on float64 streams (feasible and infeasible seeds)."""
+    p = I.volume_com(seed, grid=(48, 24, 24), dtype=np.float64)
+    say("volume_com f64", seed, p.n)
+    x, r, fm = run(ctx, p)
+    assert x.dtype == np.float64
+    check(p, x, r, orc(p), fm)
+
+
 def test_volume_com_ragged_2d(ctx):
     """n = 2 * 37^2 = 2738 is not a multiple of the vector width: rows are padded."""
     p = I.volume_com(2, grid=(74, 37))
