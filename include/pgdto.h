@@ -334,6 +334,13 @@ int pgdto_batch_stats(pgdto_batch* b, int64_t* admitted, int64_t* completed, int
 /* Cancels queued requests, waits for in-flight ones, releases resources. */
 int pgdto_batch_destroy(pgdto_batch* b);
 
+/* Host-only validation of a projection request: the checks pgdto_project,
+ * pgdto_project_async and pgdto_batch_submit make before anything is
+ * launched (kinds, sizes, alignment of the device pointers, box, C,
+ * eq_mask, block offsets, params; params may be NULL for the defaults).  No
+ * device memory is read and no device is needed.  PGDTO_OK or
+ * PGDTO_ERR_ARG. */
+int pgdto_problem_check(const pgdto_problem* prob, const pgdto_params* params);
 const char* pgdto_status_string(int status);
 int pgdto_version(void);
 

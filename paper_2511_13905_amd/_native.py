@@ -117,6 +117,7 @@ SIGNATURES = {
     "pgdto_batch_destroy": (C.c_int, [_VP]),
     "pgdto_status_string": (C.c_char_p, [C.c_int]),
     "pgdto_version": (C.c_int, []),
+    "pgdto_problem_check": (C.c_int, [C.POINTER(Problem), C.POINTER(Params)]),
     "pgdto_struct_size": (C.c_size_t, [C.c_int]),
     "pgdto_trace_read": (C.c_int, [_VP, C.POINTER(C.c_uint64), C.c_int]),
 }

@@ -66,6 +66,14 @@ extern "C" const char* pgdto_status_string(int s) {
 
 extern "C" int pgdto_version(void) { return PGDTO_VERSION; }
 
+extern "C" int pgdto_problem_check(const pgdto_problem* prob, const pgdto_params* params) {
+  if (!prob) return PGDTO_ERR_ARG;
+  pgdto_params pp;
+  if (params) pp = *params; else pgdto_params_default(&pp);
+  Desc d;
+  return build_desc(prob, &pp, true, d);
+}
+
 extern "C" int pgdto_trace_read(pgdto_ctx* c, uint64_t* out, int max_records) {
   if (!c || !out) return PGDTO_ERR_ARG;
   if (!c->trace) return 0;

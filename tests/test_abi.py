@@ -53,3 +53,63 @@ def test_null_arguments_are_rejected_without_a_device():
     p = N.Params()
     L.pgdto_params_default(ctypes.byref(p))
     assert p.tol_b == 1e-8 and p.max_newton == 50 and p.c1 == 1e-4 and p.c2 == 0.9
+
+
+def _problem(N, kind="single", m=1, n=1000, dtype=0, lda=None, b=None, offsets=None, C=float("inf"),
+             lo=1e-3, hi=1.0, eq=0, y=0x100000, A=0x200000, x=0x300000, mask=None):
+    """A problem struct with fake (never dereferenced) device addresses."""
+    p = N.Problem()
+    p.kind = N.KINDS[kind]
+    p.dtype = dtype
+    p.n = n
+    p.m = m
+    p.y, p.A, p.x = y, A, x
+    p.lda = n if lda is None else lda
+    keep = [(ctypes.c_double * m)(*(b if b is not None else [0.5] * m))]
+    p.b = ctypes.cast(keep[0], ctypes.POINTER(ctypes.c_double))
+    if offsets is not None:
+        keep.append((ctypes.c_int64 * len(offsets))(*offsets))
+        p.block_offsets = ctypes.cast(keep[-1], ctypes.POINTER(ctypes.c_int64))
+    p.lo, p.hi, p.C = lo, hi, C
+    p.free_mask = mask
+    p.eq_mask = eq
+    return p, keep
+
+
+def test_host_validation_without_a_device():
+    """pgdto_problem_check: the host-side argument rules, with no GPU."""
+    from paper_2511_13905_amd import _native as N
+    L = N.lib()
+    chk = lambda **kw: L.pgdto_problem_check(ctypes.byref(_problem(N, **kw)[0]), None)
+    assert chk() == N.OK
+    assert chk(kind="coupled", m=3, lda=1000) == N.OK
+    assert chk(kind="coupled", m=3, lda=1001) == N.ERR_ARG            # rows not 16-byte aligned
+    assert chk(kind="coupled", m=3, lda=999) == N.ERR_ARG             # lda < n
+    assert chk(kind="coupled", m=9, lda=1000) == N.ERR_ARG            # m > PGDTO_MAX_M
+    assert chk(kind="single", m=2) == N.ERR_ARG
+    assert chk(n=0) == N.ERR_ARG
+    assert chk(y=0x100004) == N.ERR_ARG                               # misaligned y
+    assert chk(x=0x200000) == N.ERR_ARG                               # x aliases A
+    assert chk(mask=0x400002) == N.ERR_ARG                            # misaligned mask
+    assert chk(lo=1.0, hi=1.0) == N.ERR_ARG
+    assert chk(lo=float("nan")) == N.ERR_ARG
+    assert chk(b=[float("nan")]) == N.ERR_ARG and chk(b=[float("inf")]) == N.ERR_ARG   # b finite
+    # C: > 0 or INFINITY; < 0 asks for the automatic penalty; 0, NaN, -INFINITY rejected
+    assert chk(C=1e12) == N.OK and chk(C=-1e-6) == N.OK
+    assert chk(C=0.0) == N.ERR_ARG and chk(C=float("nan")) == N.ERR_ARG and chk(C=float("-inf")) == N.ERR_ARG
+    # equality rows: bits below m only
+    assert chk(eq=1) == N.OK and chk(eq=2) == N.ERR_ARG
+    assert chk(kind="coupled", m=3, lda=1000, eq=0b101) == N.OK
+    assert chk(kind="coupled", m=3, lda=1000, eq=0b1000) == N.ERR_ARG
+    # independent blocks: offsets from 0 to n, strictly increasing
+    assert chk(kind="independent", m=2, offsets=[0, 400, 1000]) == N.OK
+    assert chk(kind="independent", m=2, offsets=[0, 400, 999]) == N.ERR_ARG
+    assert chk(kind="independent", m=2, offsets=[0, 0, 1000]) == N.ERR_ARG
+    assert chk(kind="independent", m=2, offsets=[1, 400, 1000]) == N.ERR_ARG
+    # params
+    p, keep = _problem(N)
+    prm = N.Params()
+    L.pgdto_params_default(ctypes.byref(prm))
+    assert L.pgdto_problem_check(ctypes.byref(p), ctypes.byref(prm)) == N.OK
+    prm.tol_n = 0.0
+    assert L.pgdto_problem_check(ctypes.byref(p), ctypes.byref(prm)) == N.ERR_ARG
