@@ -11,7 +11,7 @@ struct pgdto_ctx {
   int device = 0;
   double* part = nullptr;        // per-tile partial sums, double-buffered
   uint64_t* sync = nullptr;      // grid synchronisation words
-  uint64_t launch_seq = 0;       // epoch base of the next launch
+  uint64_t launch_seq = 0;       // launches so far (the kernel takes its epochs from the door)
   void* res_dev = nullptr;       // device staging of a result struct
   void* res_host = nullptr;      // pinned host staging
   uint64_t* trace = nullptr;     // per-pass timestamps when PGDTO_TRACE is set

@@ -1,5 +1,6 @@
-// Host side of the C ABI: argument validation, tiling, cooperative launch,
-// result retrieval.  No allocation happens on the call path: the context owns
+// Host side of the C ABI: argument validation, tiling, the launch (an
+// ordinary one; the kernel's arrival door admits the workgroups), result
+// retrieval.  No allocation happens on the call path: the context owns
 // a fixed workspace sized for the largest tile table.
 
 #include <hip/hip_runtime.h>

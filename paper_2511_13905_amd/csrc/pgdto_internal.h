@@ -61,7 +61,8 @@ struct Desc {
   // workspace
   double* part;          // [2][VMAX][TILES_PAD]
   uint64_t* sync;        // epoch flags, go word, error word, totals
-  uint64_t epoch0;       // launch-unique epoch base (pass p publishes epoch0 + p + 1)
+  uint64_t epoch0;       // epoch base (pass p publishes epoch0 + p + 1): from the arrival
+                         // door's generation in one-instance launches, per job in the server
   void* result;          // pgdto_result (pgd: pgdto_pgd_out)
   uint64_t* trace;       // optional [TRACE_MAX][4] per-pass timestamps (workgroup 0)
 };

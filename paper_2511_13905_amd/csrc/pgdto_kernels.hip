@@ -1,6 +1,6 @@
 // Projection kernels for gfx950 (CDNA4, wave64).
 //
-// One persistent cooperative launch solves a whole projection: every pass
+// One persistent launch solves a whole projection: every pass
 // streams y (and the constraint rows) once, each workgroup reduces its tiles
 // into per-tile partial sums and publishes an epoch flag; workgroup 0 sums
 // the per-tile partials in a fixed order and broadcasts the totals; then
@@ -14,10 +14,12 @@
 // single-active candidates, semismooth Newton with line search, Appendix
 // A.2), Algorithm 3 (step size eq. final_alpha, direction eq. CG).
 //
-// Precision: streams are float32 or float64 in HBM; every per-element
-// operation is done in float64 (the FP64 vector rate of CDNA4 is half the
-// FP32 rate, far above what an 8 B/element stream needs), sums are float64
-// per thread, then a fixed LDS/wave tree, then a fixed-order cross-tile sum.
+// Precision: streams are float32 or float64 in HBM; per-element arithmetic
+// is float64 (float64 vector FMA runs at the rate of unpacked float32 on
+// CDNA4), sums are float64 per thread, then a fixed LDS/wave tree, then a
+// fixed-order cross-tile sum.  The one exception is the free-slope sum of the
+// 1-D search with float streams, which only steers the choice of trial points
+// and is summed in float.
 
 #include "pgdto_internal.h"
 
