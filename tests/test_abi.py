@@ -113,3 +113,43 @@ def test_host_validation_without_a_device():
     assert L.pgdto_problem_check(ctypes.byref(p), ctypes.byref(prm)) == N.OK
     prm.tol_n = 0.0
     assert L.pgdto_problem_check(ctypes.byref(p), ctypes.byref(prm)) == N.ERR_ARG
+
+
+C_PROGRAM = r"""
+#include <math.h>
+#include <stdio.h>
+#include "pgdto.h"
+int main(void) {
+  pgdto_ctx* ctx = NULL;
+  if (pgdto_ctx_create(0, &ctx) != PGDTO_OK) return 1;
+  const int64_t n = 1024;
+  double b[1] = {0.5};
+  pgdto_problem p = {PGDTO_SINGLE, PGDTO_F32, n, 1, (void*)0, (void*)0, n, NULL, b, 1e-3, 1.0, INFINITY,
+                     (void*)0, NULL, 0};
+  pgdto_params prm;
+  pgdto_params_default(&prm);
+  printf("%d\n", pgdto_problem_check(&p, &prm));
+  pgdto_result res;
+  int st = pgdto_project(ctx, &p, &prm, &res, NULL);
+  pgdto_ctx_destroy(ctx);
+  return st == PGDTO_OK ? 0 : 2;
+}
+"""
+
+
+def test_c_program_builds_against_the_header(tmp_path):
+    """A C program (not C++) includes the header and links the library: the
+    boundary is plain C.  Compiled and linked only; nothing is run."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(C_PROGRAM)
+    out = tmp_path / "use"
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-o", str(out), "-L", os.path.dirname(LIB), "-lpgdto", "-lm",
+                        "-Wl,--unresolved-symbols=ignore-in-shared-libs"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

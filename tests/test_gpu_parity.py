@@ -373,6 +373,32 @@ def test_late_arrivals_give_the_same_bits(ctx):
                 pg.append((x.cpu().numpy(), d.cpu().numpy(), out))
             assert np.array_equal(pg[0][0], pg[1][0]) and np.array_equal(pg[0][1], pg[1][1])
             assert pg[0][2]["alpha"] == pg[1][2]["alpha"] and pg[0][2]["proj"]["lam"] == pg[1][2]["proj"]["lam"]
+        # Algorithm 3 on coupled rows and on independent blocks
+        rng = np.random.default_rng(31)
+        pc = I.volume_com(0, grid=(48, 24, 24))
+        blocks = np.array([0, 30011, 60022, pc.n], dtype=np.int64)
+        cases = [("coupled", pc.A, pc.b.copy(), pc.C, None),
+                 ("independent", np.full(pc.n, 1.0 / 30011, dtype=np.float32), np.array([0.3, 0.25, 0.2]),
+                  math.inf, blocks)]
+        rho = np.clip(rng.uniform(0, 0.6, pc.n), I.LO, I.HI).astype(np.float32)
+        grad = rng.standard_normal(pc.n).astype(np.float32)
+        rho_prev = (rho - 0.01 * rng.standard_normal(pc.n)).astype(np.float32)
+        grad_prev = (grad + 0.1 * rng.standard_normal(pc.n)).astype(np.float32)
+        for kind, A, G, Cp, offs in cases:
+            A64 = np.atleast_2d(A.astype(np.float64))
+            if kind == "independent":
+                g = np.array([float(A64[0, offs[j]:offs[j + 1]] @ rho[offs[j]:offs[j + 1]]) for j in range(3)])
+            else:
+                g = A64 @ rho.astype(np.float64)
+            pg = []
+            for c in (c0, ctx):
+                d = dev(-grad_prev)
+                x, out = c.pgd_step(kind, dev(A), dev(rho), dev(rho_prev), dev(grad), dev(grad_prev), d, g, G, 70,
+                                    I.LO, I.HI, C=Cp, offsets=offs)
+                torch.cuda.synchronize()
+                pg.append((x.cpu().numpy(), d.cpu().numpy(), out))
+            assert np.array_equal(pg[0][0], pg[1][0]) and np.array_equal(pg[0][1], pg[1][1]), kind
+            assert pg[0][2]["proj"]["lam"] == pg[1][2]["proj"]["lam"], kind
     finally:
         c0.close()
 
