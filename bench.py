@@ -53,11 +53,11 @@ def parse():
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
 MEASURED_TRAFFIC = {
     # profiles/k_solve_1d_f32_pgd_compliance_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "358bdb26c6a619c9", "bytes_per_launch": 215424526,
-                       "read": 180530762, "written": 34893764},
+    "pgd_compliance": {"kernel_sha": "5b2747caa59a33f6", "bytes_per_launch": 223412028,
+                       "read": 180708724, "written": 42703304},
     # profiles/k_solve_1d_f32_project_compliance_hbm_traffic.md
-    "project_compliance": {"kernel_sha": "358bdb26c6a619c9", "bytes_per_launch": 54142767,
-                           "read": 36106927, "written": 18035840},
+    "project_compliance": {"kernel_sha": "5b2747caa59a33f6", "bytes_per_launch": 54126668,
+                           "read": 36086876, "written": 18039792},
 }
 
 

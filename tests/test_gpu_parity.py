@@ -376,9 +376,9 @@ def test_late_arrivals_give_the_same_bits(ctx):
         # Algorithm 3 on coupled rows and on independent blocks
         rng = np.random.default_rng(31)
         pc = I.volume_com(0, grid=(48, 24, 24))
-        blocks = np.array([0, 30011, 60022, pc.n], dtype=np.int64)
+        blocks = np.array([0, 9001, 18002, pc.n], dtype=np.int64)
         cases = [("coupled", pc.A, pc.b.copy(), pc.C, None),
-                 ("independent", np.full(pc.n, 1.0 / 30011, dtype=np.float32), np.array([0.3, 0.25, 0.2]),
+                 ("independent", np.full(pc.n, 1.0 / 9001, dtype=np.float32), np.array([0.3, 0.25, 0.2]),
                   math.inf, blocks)]
         rho = np.clip(rng.uniform(0, 0.6, pc.n), I.LO, I.HI).astype(np.float32)
         grad = rng.standard_normal(pc.n).astype(np.float32)
