@@ -7,7 +7,11 @@ step.  Inputs are synthetic (seeded), resident in HBM before timing; steps
 rotate over several independent instances whose combined footprint exceeds
 the 256 MB Infinity Cache, so every step reads its inputs from HBM.
 
-Prints one JSON line (see the design doc for every field's definition).
+Prints one JSON line: the metric, throughput and latency of the timed steps,
+the roofline of the kernel (algorithmic bytes per launch over the launch time
+from HIP events, measured HBM traffic when the kernel source matches the
+profiled one), the CPU oracle's rate and the error against it, and the
+served-stream and batched measurements.
 """
 from __future__ import annotations
 
@@ -93,8 +97,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
