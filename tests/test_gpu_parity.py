@@ -330,6 +330,45 @@ def test_graph_replay_matches_eager(ctx):
         torch.cuda.synchronize()
 
 
+def test_graph_replay_pgd_step(ctx):
+    """pgd_step_async captured once and replayed three times (d is updated in
+    place, so every replay is the next step of the same sequence) gives the
+    bits of three eager steps."""
+    from paper_2511_13905_amd.api import result_from_bytes, result_nbytes
+    st = I.pgd_compliance_3d(4, t=60, n=150001)
+    say("graph replay pgd_step", st.rho.size)
+    A, rho, rp, gr, gp = (dev(v) for v in (st.problem.A, st.rho, st.rho_prev, st.grad, st.grad_prev))
+    # eager reference: three steps on one direction buffer
+    d_e = dev(st.d_prev)
+    eager = []
+    for _ in range(3):
+        x, out = ctx.pgd_step("single", A, rho, rp, gr, gp, d_e, st.g, st.G, st.t, I.LO, I.HI)
+        torch.cuda.synchronize()
+        eager.append((x.cpu().numpy(), d_e.cpu().numpy(), out))
+    d_g = dev(st.d_prev)
+    x_g = torch.empty_like(rho)
+    res = torch.zeros(result_nbytes(pgd=True), dtype=torch.uint8, device="cuda:0")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):                     # warm-up outside the capture, on a scratch d
+        d_w = dev(st.d_prev)
+        ctx.pgd_step_async("single", A, rho, rp, gr, gp, d_w, st.g, st.G, st.t, I.LO, I.HI, res, x=x_g)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.pgd_step_async("single", A, rho, rp, gr, gp, d_g, st.g, st.G, st.t, I.LO, I.HI, res, x=x_g)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        xe, de, oe = eager[k]
+        assert np.array_equal(x_g.cpu().numpy(), xe), k
+        assert np.array_equal(d_g.cpu().numpy(), de), k
+        og = result_from_bytes(res, pgd=True)
+        assert og["alpha"] == oe["alpha"] and og["proj"]["lam"] == oe["proj"]["lam"], k
+
+
 def test_late_arrivals_give_the_same_bits(ctx):
     """An arrival door that closes at the first arrival (PGDTO_DOOR_WAIT=0)
     leaves most of the grid out: the participants solve every tile, late
