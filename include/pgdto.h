@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 2      /* 2: eq_mask, automatic C, pgdto_result.kappa */
+#define PGDTO_VERSION 3      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0 */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
@@ -132,6 +132,17 @@ typedef struct {
                                    either sign, lambda[j] < 0 when the row is
                                    raised to its target); 0: all A x <= b.
                                    Bits at or above m: PGDTO_ERR_ARG           */
+  const double* lambda0;        /* optional host [m]: warm start, e.g. the
+                                   multipliers of the previous Algorithm 3
+                                   iteration; NULL: cold start.  Finite, >= 0
+                                   for inequality rows (else PGDTO_ERR_ARG).
+                                   Changes the search path, not the problem:
+                                   1-D rows evaluate lambda0[j] in the first
+                                   search pass, beside the cold first trial,
+                                   when it lies inside the bracket (0, largest
+                                   breakpoint) and ignore it otherwise;
+                                   COUPLED starts the Newton iteration at
+                                   lambda0 instead of Stage 1                 */
 } pgdto_problem;
 
 typedef struct {

@@ -34,7 +34,8 @@ class Problem(C.Structure):
                 ("y", C.c_void_p), ("A", C.c_void_p), ("lda", C.c_int64),
                 ("block_offsets", C.POINTER(C.c_int64)), ("b", C.POINTER(C.c_double)),
                 ("lo", C.c_double), ("hi", C.c_double), ("C", C.c_double),
-                ("x", C.c_void_p), ("free_mask", C.c_void_p), ("eq_mask", C.c_uint64)]
+                ("x", C.c_void_p), ("free_mask", C.c_void_p), ("eq_mask", C.c_uint64),
+                ("lambda0", C.POINTER(C.c_double))]
 
 
 class Params(C.Structure):

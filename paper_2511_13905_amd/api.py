@@ -83,10 +83,11 @@ def eq_mask_of(eq) -> int:
 
 
 def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, free_mask=None,
-                   keep: _Keep | None = None, copy_ok: bool = True, eq=None):
+                   keep: _Keep | None = None, copy_ok: bool = True, eq=None, lam0=None):
     """Fill a pgdto_problem from torch tensors; returns (struct, x, A_used).
     copy_ok=False: raise instead of copying A into 16-byte aligned rows.
-    eq: rows / blocks held at equality (flags or a bit mask)."""
+    eq: rows / blocks held at equality (flags or a bit mask).
+    lam0: optional warm-start multipliers, one per row / block."""
     keep = keep or _Keep()
     k = N.KINDS[kind] if isinstance(kind, str) else int(kind)
     if y is not None and not y.is_contiguous():
@@ -124,6 +125,7 @@ def problem_struct(kind, y, A, b, lo, hi, C_pen=math.inf, offsets=None, x=None, 
     s.x = x.data_ptr()
     s.free_mask = free_mask.data_ptr() if free_mask is not None else None
     s.eq_mask = eq_mask_of(eq)
+    s.lambda0 = keep.dbl(list(lam0)) if lam0 is not None else None
     return s, x, A_used
 
 
@@ -167,10 +169,10 @@ class Context:
 
     # ------------------------------------------------------------ projection
     def project(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None,
-                params: N.Params | dict | None = None, stream=None, eq=None):
+                params: N.Params | dict | None = None, stream=None, eq=None, lam0=None):
         """pgdto_project: returns (x, result dict).  Blocks until done."""
         keep = _Keep()
-        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq)
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq, lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         r = N.Result()
         st = N.lib().pgdto_project(self.h, C_byref(s), C_byref(p), C_byref(r), _stream(self.device, stream))
@@ -178,11 +180,11 @@ class Context:
         return x, r.to_dict()
 
     def project_async(self, kind, y, A, b, lo, hi, result_buf: torch.Tensor, C=math.inf, offsets=None,
-                      x=None, free_mask=None, params=None, stream=None, eq=None):
+                      x=None, free_mask=None, params=None, stream=None, eq=None, lam0=None):
         """pgdto_project_async: enqueue only; the result struct lands in result_buf
         (uint8 device tensor of at least sizeof(pgdto_result) bytes)."""
         keep = _Keep()
-        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq)
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq, lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         st = N.lib().pgdto_project_async(self.h, C_byref(s), C_byref(p), result_buf.data_ptr(),
                                          _stream(self.device, stream))
@@ -191,9 +193,9 @@ class Context:
 
     # ------------------------------------------------------------ Alg. 3 step
     def _pgd_struct(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                    hyper, keep, copy_ok=True, eq=None):
+                    hyper, keep, copy_ok=True, eq=None, lam0=None):
         s, x, _A = problem_struct(kind, None, A, None, lo, hi, C, offsets, x if x is not None else
-                                  torch.empty_like(rho), None, keep, copy_ok=copy_ok, eq=eq)
+                                  torch.empty_like(rho), None, keep, copy_ok=copy_ok, eq=eq, lam0=lam0)
         a = N.PgdArgs()
         N.lib().pgdto_pgd_args_default(C_byref(a))
         a.proj = s
@@ -212,12 +214,13 @@ class Context:
         return a, x
 
     def pgd_step(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf,
-                 offsets=None, x=None, params=None, stream=None, eq=None, **hyper):
+                 offsets=None, x=None, params=None, stream=None, eq=None, lam0=None, **hyper):
         """pgdto_pgd_step: one Alg. 3 body.  d is updated in place (d_{t-1} -> d_t);
-        returns (rho_{t+1}, out dict)."""
+        returns (rho_{t+1}, out dict).  lam0: warm start of the projection
+        (e.g. out["proj"]["lam"] of the previous step)."""
         keep = _Keep()
         a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                hyper, keep, eq=eq)
+                                hyper, keep, eq=eq, lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         out = N.PgdOut()
         st = N.lib().pgdto_pgd_step(self.h, C_byref(a), C_byref(p), C_byref(out), _stream(self.device, stream))
@@ -225,10 +228,10 @@ class Context:
         return x, out.to_dict()
 
     def pgd_step_async(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, out_buf,
-                       C=math.inf, offsets=None, x=None, params=None, stream=None, **hyper):
+                       C=math.inf, offsets=None, x=None, params=None, stream=None, lam0=None, **hyper):
         keep = _Keep()
         a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                hyper, keep)
+                                hyper, keep, lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         st = N.lib().pgdto_pgd_step_async(self.h, C_byref(a), C_byref(p), out_buf.data_ptr(),
                                           _stream(self.device, stream))
@@ -281,9 +284,10 @@ class Batch:
         return s.value, w.value
 
     def submit(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None, params=None,
-               eq=None) -> int:
+               eq=None, lam0=None) -> int:
         keep = _Keep()
-        s, x, A_used = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, copy_ok=False, eq=eq)
+        s, x, A_used = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, copy_ok=False, eq=eq,
+                                      lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         t = C_u64()
         _check(N.lib().pgdto_batch_submit(self.h, C_byref(s), C_byref(p), C_byref(t)), "pgdto_batch_submit")
@@ -291,13 +295,13 @@ class Batch:
         return t.value
 
     def submit_pgd(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf, offsets=None,
-                   x=None, params=None, **hyper) -> int:
+                   x=None, params=None, lam0=None, **hyper) -> int:
         """pgdto_batch_submit_pgd: one Algorithm 3 step as a served request
         (d is updated in place, rho_{t+1} lands in x).  A must already have
         16-byte aligned rows; the data must be complete when this is called."""
         keep = _Keep()
         a, x = self.ctx._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                    hyper, keep, copy_ok=False)
+                                    hyper, keep, copy_ok=False, lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         tk = C_u64()
         _check(N.lib().pgdto_batch_submit_pgd(self.h, C_byref(a), C_byref(p), C_byref(tk)), "pgdto_batch_submit_pgd")

@@ -228,6 +228,15 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   d.hi = pr->hi;
   if (pr->m < 64 && (pr->eq_mask >> pr->m) != 0) return PGDTO_ERR_ARG;
   d.eq_mask = pr->eq_mask;
+  if (pr->lambda0) {
+    for (int j = 0; j < pr->m; ++j) {
+      const double l = pr->lambda0[j];
+      const bool eq = (pr->eq_mask >> j) & 1ull;
+      if (!isfinite(l) || (!eq && l < 0.0)) return PGDTO_ERR_ARG;
+      d.lam0[j] = l;
+    }
+    d.warm = 1;
+  }
   d.auto_tau = pr->C < 0.0 ? -pr->C : 0.0;
   d.kappa = (pr->C < 0.0 || isinf(pr->C)) ? 0.0 : 2.0 / pr->C;
   d.tol_b = pp->tol_b;

@@ -44,6 +44,8 @@ struct Desc {
   double tol_b, tol_n, c1, c2;
   int32_t max_search, max_newton, max_ls, search, ncp, stage1;
   double b[PGDTO_MAX_BLOCKS];          // right-hand sides (pgd: G - g)
+  double lam0[PGDTO_MAX_BLOCKS];       // warm start (warm != 0)
+  int32_t warm;
   int64_t off[PGDTO_MAX_BLOCKS + 1];   // segment bounds (single/coupled: 0, n)
   int32_t tile_base[PGDTO_MAX_BLOCKS + 1];
   int64_t tile_elems;

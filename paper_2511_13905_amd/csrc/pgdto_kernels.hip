@@ -580,6 +580,17 @@ __device__ __forceinline__ bool search_init(Search& S, int s, double f0, double 
   return true;
 }
 
+// Warm start: the first pass evaluates lam0 (when inside the bracket) and
+// the cold first trial as its second trial.  A lam0 within the stop
+// tolerance ends the search in that pass; otherwise the bracket update keeps
+// whichever of the two ends up closer, and the search goes on from there.
+__device__ __forceinline__ void search_warm(Search& S, int s, double lam0) {
+  if (!inside(lam0, S.lo[s], S.hi[s])) return;
+  const double t0 = S.trial[s][0];
+  S.trial[s][0] = lam0;
+  S.trial[s][1] = (t0 == lam0) ? NAN : t0;
+}
+
 // Update row/block s from the sums of one search pass.  fsum[t] = a.x(trial_t),
 // ssum[t] = sum over free elements of a^2 at trial_t.
 __device__ __forceinline__ void search_update(Search& S, int s, double f0sum, double f1sum, double s0sum, double s1sum,
@@ -1185,10 +1196,14 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           // inequality (-a).x <= -b is the active one; search it for
           // lam' >= 0 and report lam = -lam'
           sh.sg[s] = -1.0;
-          if constexpr (EQ)
-            search_init(sh.S, s, -f0, t[1] + kappa, t[6], -t[7], -sh.bs[s], kappa, scale, d.search, true);
+          if constexpr (EQ) {
+            if (search_init(sh.S, s, -f0, t[1] + kappa, t[6], -t[7], -sh.bs[s], kappa, scale, d.search, true) &&
+                d.warm)
+              search_warm(sh.S, s, -d.lam0[s]);
+          }
         } else {
-          search_init(sh.S, s, f0, t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search, true);
+          if (search_init(sh.S, s, f0, t[1] + kappa, t[2], t[3], sh.bs[s], kappa, scale, d.search, true) && d.warm)
+            search_warm(sh.S, s, d.lam0[s]);
           if (eq && sh.S.outcome[s] == PGDTO_INACTIVE) sh.S.outcome[s] = PGDTO_CONVERGED;   // h(0) = 0
         }
       }
@@ -2001,7 +2016,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         sh.S.scale[j] = scale;
         sh.N.h0[j] = t[j] - sh.bs[j];
         sh.S.ssat[j] = t[3 * M + j];
-        if (d.stage1 && !d.eq_mask && t[5 * M] == 0.0) {
+        if (d.stage1 && !d.eq_mask && !d.warm && t[5 * M] == 0.0) {
           search_init(sh.S, j, t[j] - sh.bs[j], t[M + j] + kappa, t[2 * M + j], t[3 * M + j], sh.bs[j], kappa,
                       scale, d.search, false);
         } else {
@@ -2021,11 +2036,12 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           sh.outcome = PGDTO_INACTIVE;
           sh.path = 0;
           sh.phase = PH_FINAL;
-        } else if (!d.stage1 || d.eq_mask) {
+        } else if (!d.stage1 || d.eq_mask || d.warm) {
           // Stage 1 tests single active rows; equality rows are always
-          // active, so with any of them Newton starts at lam = 0
+          // active, so with any of them Newton starts at lam = 0; a warm
+          // start begins Newton at the given multipliers
           sh.path = 3;
-          for (int j = 0; j < M; ++j) sh.N.trial[j] = 0.0;
+          for (int j = 0; j < M; ++j) sh.N.trial[j] = d.warm ? d.lam0[j] : 0.0;
           sh.N.init = 1;
           sh.phase = PH_NEWTON;
         } else {

@@ -39,7 +39,7 @@ def test_struct_layouts_match_binding():
     L = N.lib()
     for i, S in enumerate(N.STRUCTS):
         assert L.pgdto_struct_size(i) == ctypes.sizeof(S), S.__name__
-    assert L.pgdto_version() == 2
+    assert L.pgdto_version() == 3
     assert N.status_string(N.ERR_ARG) == "invalid argument"
 
 
@@ -56,7 +56,7 @@ def test_null_arguments_are_rejected_without_a_device():
 
 
 def _problem(N, kind="single", m=1, n=1000, dtype=0, lda=None, b=None, offsets=None, C=float("inf"),
-             lo=1e-3, hi=1.0, eq=0, y=0x100000, A=0x200000, x=0x300000, mask=None):
+             lo=1e-3, hi=1.0, eq=0, y=0x100000, A=0x200000, x=0x300000, mask=None, lam0=None):
     """A problem struct with fake (never dereferenced) device addresses."""
     p = N.Problem()
     p.kind = N.KINDS[kind]
@@ -73,6 +73,9 @@ def _problem(N, kind="single", m=1, n=1000, dtype=0, lda=None, b=None, offsets=N
     p.lo, p.hi, p.C = lo, hi, C
     p.free_mask = mask
     p.eq_mask = eq
+    if lam0 is not None:
+        keep.append((ctypes.c_double * m)(*lam0))
+        p.lambda0 = ctypes.cast(keep[-1], ctypes.POINTER(ctypes.c_double))
     return p, keep
 
 
@@ -101,6 +104,13 @@ def test_host_validation_without_a_device():
     assert chk(eq=1) == N.OK and chk(eq=2) == N.ERR_ARG
     assert chk(kind="coupled", m=3, lda=1000, eq=0b101) == N.OK
     assert chk(kind="coupled", m=3, lda=1000, eq=0b1000) == N.ERR_ARG
+    # warm start: finite; >= 0 unless the row is an equality
+    assert chk(lam0=[0.25]) == N.OK and chk(lam0=[0.0]) == N.OK
+    assert chk(lam0=[-0.25]) == N.ERR_ARG and chk(lam0=[float("nan")]) == N.ERR_ARG
+    assert chk(lam0=[float("inf")]) == N.ERR_ARG
+    assert chk(lam0=[-0.25], eq=1) == N.OK
+    assert chk(kind="coupled", m=3, lda=1000, lam0=[1.0, -2.0, 0.0], eq=0b010) == N.OK
+    assert chk(kind="coupled", m=3, lda=1000, lam0=[1.0, -2.0, 0.0], eq=0b001) == N.ERR_ARG
     # independent blocks: offsets from 0 to n, strictly increasing
     assert chk(kind="independent", m=2, offsets=[0, 400, 1000]) == N.OK
     assert chk(kind="independent", m=2, offsets=[0, 400, 999]) == N.ERR_ARG

@@ -279,6 +279,69 @@ def test_equality_rows(ctx, case):
         assert r["lam"][0] < 0.0
 
 
+
+def _warm_run(ctx, p, lam0, eq=None):
+    y, A = dev(p.y), dev(p.A)
+    mask = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+    x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=mask, eq=eq, lam0=lam0)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), r, free_from_mask(mask.cpu().numpy().view(np.uint32), p.n)
+
+
+WARM_CASES = {
+    "single": lambda: I.compliance_3d(0),
+    "independent": lambda: I.multi_material(2, fields=4, n_per=131072),
+    "coupled": lambda: I.volume_com(0, grid=(48, 24, 24)),
+    "coupled-infeasible": lambda: I.volume_com(1, grid=(48, 24, 24)),
+}
+
+
+@pytest.mark.parametrize("case", list(WARM_CASES))
+@pytest.mark.parametrize("factor", [1.0, 0.97, 1.05])
+def test_warm_start(ctx, case, factor):
+    """pgdto_problem.lambda0: a warm start changes the search path, not the
+    projection.  Started from the oracle's multipliers (scaled), the HIP path
+    still matches the oracle; from the exact ones a 1-D search ends in one
+    pass (zero pass, one search pass, final pass)."""
+    p = WARM_CASES[case]()
+    ref = orc(p)
+    lam0 = [max(0.0, float(v) * factor) for v in ref.lam]
+    say("warm start", case, factor, p.n, lam0)
+    xc, rc, _ = run(ctx, p)
+    x, r, fm = _warm_run(ctx, p, lam0)
+    check(p, x, r, ref, fm)
+    print("cold passes", rc["passes"], "warm passes", r["passes"], "path", r["path"], flush=True)
+    if p.kind != "coupled" and factor == 1.0:
+        assert r["passes"] <= 3
+    if p.kind == "coupled":
+        assert r["path"] in (0, 3)
+
+
+def test_warm_start_outside_bracket_is_ignored(ctx):
+    """A lambda0 outside the 1-D bracket [0, largest breakpoint] leaves the
+    search as it is: bitwise the cold result."""
+    p = I.compliance_3d(3, n=1000003)
+    say("warm start outside", p.n)
+    xc, rc, fc = run(ctx, p)
+    x, r, fm = _warm_run(ctx, p, [1e30])
+    assert np.array_equal(x.view(np.uint32), xc.view(np.uint32))
+    assert r["lam"] == rc["lam"] and r["passes"] == rc["passes"]
+    assert np.array_equal(fm, fc)
+
+
+@pytest.mark.parametrize("case", ["single-raise", "coupled"])
+def test_warm_start_equality_rows(ctx, case):
+    """Equality rows take a warm start of either sign."""
+    p, eq = _eq_case(case)
+    ref = oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets, eq=eq)
+    lam0 = [float(v) * 1.02 for v in ref.lam]
+    say("warm start equality", case, p.n, lam0)
+    x, r, fm = _warm_run(ctx, p, lam0, eq=eq)
+    check(p, x, r, ref, fm)
+    assert r["lam"][0] < 0.0
+    assert r["lam"][0] == pytest.approx(ref.lam[0], rel=1e-6)
+
+
 def test_graph_replay_matches_eager(ctx):
     """One-instance launches captured in a HIP graph (two projections, masks
     included) and replayed three times, with eager launches on the same

@@ -12,6 +12,9 @@ the very same float32 inputs (step size, beta, direction, the projected point
 and the stop test), so the parity bar applies per iteration; over the run the
 objective must fall and the iterates stay feasible.  The run also crosses the
 first step (fallback step size), the warm-up boundary and the PR+ restarts.
+The warm variants start each projection from the previous step's multipliers
+(pgdto_problem.lambda0) and also run the cold step on the same inputs: the
+warm run may take no more passes in total than the cold one.
 """
 import numpy as np
 import pytest
@@ -68,8 +71,10 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-@pytest.mark.parametrize("kind,rule,steps", [("single", "pr+", 70), ("single", "fr", 20), ("coupled", "pr+", 60)])
-def test_pgd_loop(ctx, kind, rule, steps):
+@pytest.mark.parametrize("kind,rule,steps,warm", [("single", "pr+", 70, False), ("single", "fr", 20, False),
+                                                 ("coupled", "pr+", 60, False), ("single", "pr+", 70, True),
+                                                 ("coupled", "pr+", 60, True)])
+def test_pgd_loop(ctx, kind, rule, steps, warm):
     nx, ny = 128, 64
     n = nx * ny
     obj = Objective(nx, ny, seed=3)
@@ -87,21 +92,30 @@ def test_pgd_loop(ctx, kind, rule, steps):
     A32 = A.astype(np.float32)
     Ad = A32.astype(np.float64)
     hyper = PgdParams(cg_rule=rule)
-    say("pgd loop", kind, rule, steps, n)
+    say("pgd loop", kind, rule, steps, n, "warm" if warm else "cold")
     rho = np.full(n, 0.4, dtype=np.float32)
     rho_prev = grad_prev = None
     d = torch.zeros(n, dtype=torch.float32, device="cuda:0")
     A_dev = dev(A32)
     fvals = []
     fallbacks = []
+    lam_prev = None
+    passes_warm = passes_cold = 0
     for t in range(steps):
         gr = obj.grad(rho.astype(np.float64)).astype(np.float32)
         g = Ad @ rho.astype(np.float64)                      # constraint values (exact for linear rows)
         d_prev = d.cpu().numpy()
-        x, out = ctx.pgd_step(kind, A_dev, dev(rho), dev(rho_prev) if rho_prev is not None else None,
-                              dev(gr), dev(grad_prev) if grad_prev is not None else None, d, g, G, t, lo, hi,
-                              C=C, cg_rule=rule)
+        args = (dev(rho), dev(rho_prev) if rho_prev is not None else None,
+                dev(gr), dev(grad_prev) if grad_prev is not None else None)
+        if warm:
+            dc = d.clone()
+            _, outc = ctx.pgd_step(kind, A_dev, *args, dc, g, G, t, lo, hi, C=C, cg_rule=rule)
+            passes_cold += outc["proj"]["passes"]
+        x, out = ctx.pgd_step(kind, A_dev, *args, d, g, G, t, lo, hi, C=C, cg_rule=rule,
+                              lam0=lam_prev if warm else None)
         torch.cuda.synchronize()
+        passes_warm += out["proj"]["passes"]
+        lam_prev = [max(0.0, v) for v in out["proj"]["lam"]]
         xs = x.cpu().numpy()
         ref = oracle.pgd_step(kind, rho, rho_prev if rho_prev is not None else rho, gr,
                               grad_prev if grad_prev is not None else gr, d_prev, A32, g, G, t, lo, hi,
@@ -129,3 +143,6 @@ def test_pgd_loop(ctx, kind, rule, steps):
         assert min(fvals) >= fvals[-1] - 1e-6 * abs(fvals[-1])
     viol = Ad @ rho.astype(np.float64) - G
     assert np.max(viol) <= 1e-5 * max(1.0, float(np.max(np.abs(G))))
+    if warm:
+        print("passes over the run: warm", passes_warm, "cold", passes_cold, flush=True)
+        assert passes_warm <= passes_cold
