@@ -57,11 +57,11 @@ def parse():
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
 MEASURED_TRAFFIC = {
     # profiles/k_solve_1d_f32_pgd_compliance_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "5b2747caa59a33f6", "bytes_per_launch": 223412028,
-                       "read": 180708724, "written": 42703304},
+    "pgd_compliance": {"kernel_sha": "4ac8e5ad421ab964", "bytes_per_launch": 193654286,
+                       "read": 158753290, "written": 34900996},
     # profiles/k_solve_1d_f32_project_compliance_hbm_traffic.md
-    "project_compliance": {"kernel_sha": "5b2747caa59a33f6", "bytes_per_launch": 54126668,
-                           "read": 36086876, "written": 18039792},
+    "project_compliance": {"kernel_sha": "4ac8e5ad421ab964", "bytes_per_launch": 54191356,
+                           "read": 36152900, "written": 18038456},
 }
 
 
