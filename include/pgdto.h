@@ -303,7 +303,7 @@ int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, const pgdto_pa
 /* An Algorithm 3 step (as pgdto_pgd_step) as a served request: the same
  * contract as pgdto_batch_submit for its device buffers (rho_t, rho_{t-1},
  * grad, grad_{t-1}, d: read; d and x: written; all ready at submit and kept
- * valid until the ticket retires); g, G and block offsets are copied.  Poll it
+ * valid until the ticket retires); g, G, block offsets and lambda0 are copied.  Poll it
  * with pgdto_batch_poll_pgd (pgdto_batch_poll returns its projection part). */
 int pgdto_batch_submit_pgd(pgdto_batch* b, const pgdto_pgd_args* args, const pgdto_params* params,
                            uint64_t* ticket);

@@ -43,6 +43,7 @@ pgdto_problem Request::problem() const {
   pgdto_problem p = pgd ? args.proj : prob;
   p.b = pgd ? nullptr : b;
   p.block_offsets = p.kind == PGDTO_INDEPENDENT ? off : nullptr;
+  p.lambda0 = warm ? lam0 : nullptr;
   return p;
 }
 
@@ -116,8 +117,15 @@ extern "C" int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, con
   for (int j = 0; j < prob->m; ++j) r.b[j] = prob->b[j];
   if (prob->kind == PGDTO_INDEPENDENT)
     for (int j = 0; j <= prob->m; ++j) r.off[j] = prob->block_offsets[j];
+  if (prob->lambda0) {
+    r.warm = 1;
+    for (int j = 0; j < prob->m; ++j) r.lam0[j] = prob->lambda0[j];
+  }
+  // host arrays live in the request from here on: the descriptor is built
+  // again at admission, after this call has returned
   r.prob.b = nullptr;
   r.prob.block_offsets = nullptr;
+  r.prob.lambda0 = nullptr;
   r.footprint = request_footprint(*prob);
   if (r.footprint > b->cfg.hbm_budget_bytes) return PGDTO_ERR_NOMEM;
   return b->submit(r, ticket);
@@ -137,8 +145,13 @@ extern "C" int pgdto_batch_submit_pgd(pgdto_batch* b, const pgdto_pgd_args* args
   for (int j = 0; j < prob->m; ++j) { r.g[j] = args->g[j]; r.G[j] = args->G[j]; }
   if (prob->kind == PGDTO_INDEPENDENT)
     for (int j = 0; j <= prob->m; ++j) r.off[j] = prob->block_offsets[j];
+  if (prob->lambda0) {
+    r.warm = 1;
+    for (int j = 0; j < prob->m; ++j) r.lam0[j] = prob->lambda0[j];
+  }
   r.args.proj.b = nullptr;
   r.args.proj.block_offsets = nullptr;
+  r.args.proj.lambda0 = nullptr;
   r.args.g = nullptr;
   r.args.G = nullptr;
   Desc d;

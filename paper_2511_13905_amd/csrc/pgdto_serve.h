@@ -21,6 +21,8 @@ struct Request {
   int m = 0;
   double b[PGDTO_MAX_BLOCKS] = {};
   int64_t off[PGDTO_MAX_BLOCKS + 1] = {};
+  double lam0[PGDTO_MAX_BLOCKS] = {};   // warm start copied at submit (warm != 0)
+  int warm = 0;
   size_t footprint = 0;
   // an Algorithm 3 step instead of a projection (pgd != 0): args with its
   // host arrays (g, G, block offsets) pointing into this request

@@ -177,6 +177,42 @@ def test_server_equality_and_automatic_penalty_bitwise(ctx):
         assert r["lam"] == rs["lam"] and r["kappa"] == rs["kappa"], (r["lam"], rs["lam"])
 
 
+
+def test_server_warm_start_bitwise(ctx):
+    """Warm-started requests (pgdto_problem.lambda0) through server slots give
+    the bits of a warm-started single launch, and the oracle's projection."""
+    from paper_2511_13905_amd.api import Batch, aligned_rows
+    cases = [I.compliance_3d(6, n=70001), I.multi_material(5, fields=3, n_per=20011),
+             I.volume_com(0, grid=(64, 32))]
+    refs = [oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets) for p in cases]
+    lam0s = [[max(0.0, 0.98 * float(v)) for v in ref.lam] for ref in refs]
+    say("server warm start", [p.n for p in cases], lam0s)
+    B = Batch(ctx, max_slots=4, slots_only=True)
+    staged = []
+    for p in cases:
+        A = dev(p.A)
+        if p.kind != "independent":
+            A = aligned_rows(A)
+        staged.append((dev(p.y), A))
+    torch.cuda.synchronize()
+    tickets = [B.submit(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, lam0=l0)
+               for p, (y, A), l0 in zip(cases, staged, lam0s)]
+    outs = []
+    for t in tickets:
+        x = B.x_of(t)
+        st, r, _ = B.wait(t)
+        torch.cuda.synchronize()
+        outs.append((st, r, x.cpu().numpy()))
+    B.close()
+    for p, ref, l0, (st, r, x) in zip(cases, refs, lam0s, outs):
+        assert st == 0
+        xs, rs = ctx.project(p.kind, dev(p.y), dev(p.A), p.b, p.lo, p.hi, p.C, offsets=p.offsets, lam0=l0)
+        torch.cuda.synchronize()
+        assert np.array_equal(x, xs.cpu().numpy()), p.kind
+        assert r["lam"] == rs["lam"] and r["passes"] == rs["passes"], (r["lam"], rs["lam"])
+        check(p, x, r, ref)
+
+
 def test_server_small_slots_stream_block_starts(ctx):
     """Independent blocks on slots of 2 workgroups: most tiles are streamed
     (not held in registers), including the tiles that open a block at an
