@@ -394,31 +394,42 @@ def stage_pgd(st):
                 d=dev(st.d_prev))
 
 
-@pytest.mark.parametrize("slots_only", [False, True])
-def test_served_pgd_steps_match_single_launch(ctx, slots_only):
+@pytest.mark.parametrize("slots_only,warm", [(False, False), (True, False), (True, True)])
+def test_served_pgd_steps_match_single_launch(ctx, slots_only, warm):
     """Algorithm 3 steps served (slots or the lone full-GPU route) give the
-    bits of pgdto_pgd_step: rho_{t+1}, d_t, alpha, beta, multipliers."""
+    bits of pgdto_pgd_step: rho_{t+1}, d_t, alpha, beta, multipliers.  warm:
+    both start their projections from the same lambda0 (1.01 x the cold
+    step's multipliers), which the served request copies at submit."""
     from paper_2511_13905_amd.api import Batch
     states = pgd_states()
-    say("served pgd steps", slots_only, [s.problem.n for s in states])
+    say("served pgd steps", slots_only, "warm" if warm else "cold", [s.problem.n for s in states])
+    lam0s = [None] * len(states)
+    if warm:
+        for i, st in enumerate(states):
+            dv0 = stage_pgd(st)
+            _, o0 = ctx.pgd_step(st.problem.kind, dv0["A"], dv0["rho"], dv0["rp"] if st.t > 0 else None, dv0["gr"],
+                                 dv0["gp"] if st.t > 0 else None, dv0["d"], st.g, st.G, st.t, I.LO, I.HI,
+                                 C=st.problem.C)
+            lam0s[i] = [1.01 * max(0.0, v) for v in o0["proj"]["lam"]]
     served = [stage_pgd(s) for s in states]
     single_in = [stage_pgd(s) for s in states]
     torch.cuda.synchronize()
     B = Batch(ctx, max_slots=4, slots_only=slots_only)
     tickets = []
-    for st, dv in zip(states, served):
+    for st, dv, l0 in zip(states, served, lam0s):
         t = B.submit_pgd(st.problem.kind, dv["A"], dv["rho"], dv["rp"] if st.t > 0 else None, dv["gr"],
-                         dv["gp"] if st.t > 0 else None, dv["d"], st.g, st.G, st.t, I.LO, I.HI, C=st.problem.C)
+                         dv["gp"] if st.t > 0 else None, dv["d"], st.g, st.G, st.t, I.LO, I.HI, C=st.problem.C,
+                         lam0=l0)
         tickets.append(t)
     xs = [B.x_of(t) for t in tickets]
     outs = [B.poll_pgd(t, wait=True) for t in tickets]
     B.close()
     torch.cuda.synchronize()
-    for st, dv, dv1, x, (status, o, times) in zip(states, served, single_in, xs, outs):
+    for st, dv, dv1, x, (status, o, times), l0 in zip(states, served, single_in, xs, outs, lam0s):
         assert status == 0, status
         x1, o1 = ctx.pgd_step(st.problem.kind, dv1["A"], dv1["rho"], dv1["rp"] if st.t > 0 else None, dv1["gr"],
                               dv1["gp"] if st.t > 0 else None, dv1["d"], st.g, st.G, st.t, I.LO, I.HI,
-                              C=st.problem.C)
+                              C=st.problem.C, lam0=l0)
         torch.cuda.synchronize()
         assert torch.equal(x, x1)
         assert torch.equal(dv["d"], dv1["d"])
