@@ -348,7 +348,8 @@ int pgdto_batch_destroy(pgdto_batch* b);
 /* Host-only validation of a projection request: the checks pgdto_project,
  * pgdto_project_async and pgdto_batch_submit make before anything is
  * launched (kinds, sizes, alignment of the device pointers, box, C,
- * eq_mask, block offsets, params; params may be NULL for the defaults).  No
+ * eq_mask, lambda0, block offsets, params; params may be NULL for the
+ * defaults).  No
  * device memory is read and no device is needed.  PGDTO_OK or
  * PGDTO_ERR_ARG. */
 int pgdto_problem_check(const pgdto_problem* prob, const pgdto_params* params);

@@ -170,7 +170,8 @@ class Context:
     # ------------------------------------------------------------ projection
     def project(self, kind, y, A, b, lo, hi, C=math.inf, offsets=None, x=None, free_mask=None,
                 params: N.Params | dict | None = None, stream=None, eq=None, lam0=None):
-        """pgdto_project: returns (x, result dict).  Blocks until done."""
+        """pgdto_project: returns (x, result dict).  Blocks until done.
+        eq: rows / blocks held at equality; lam0: warm-start multipliers."""
         keep = _Keep()
         s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, eq=eq, lam0=lam0)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
