@@ -163,3 +163,25 @@ def test_c_program_builds_against_the_header(tmp_path):
                         "-Wl,--unresolved-symbols=ignore-in-shared-libs"],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises ImportError: there is no
+    CPU fallback behind the product path."""
+    from paper_2511_13905_amd import _native as N
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "libpgdto.so"))
+    with pytest.raises(ImportError):
+        N.lib()
+
+
+def test_product_package_does_not_import_the_oracle():
+    """The package (binding and API) loads without touching oracle/, which is
+    test infrastructure only."""
+    import subprocess
+    import sys
+    code = ("import sys; import paper_2511_13905_amd, paper_2511_13905_amd.api, paper_2511_13905_amd._native; "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "assert not bad, bad")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
