@@ -335,14 +335,14 @@ def serve_bench(ctx, args):
     out["server_saturated"] = _stream_stats(t, s, ns)
     out["server_shape"] = {"slots": shape[0], "wg_per_slot": shape[1]}
     # the throughput-oriented shape: the executor autotuner on the served mix
-    from paper_2511_13905_amd.api import batch_autotune
+    from paper_2511_13905_amd.api import TUNE_SLOTS, batch_autotune
     (ts, tw), cand = batch_autotune(
         ctx, [(p.kind, y, A, p.b, p.lo, p.hi, p.C, p.offsets, x) for p, (y, A), x in zip(pool, dev, xs[:P])],
         count=512, params=params)
     t, s, shape = _run_stream(ctx, structs, params, ts, zero, tw)
     out["server_saturated_tuned"] = _stream_stats(t, s, ns)
     out["server_saturated_tuned"]["shape"] = {"slots": shape[0], "wg_per_slot": shape[1]}
-    out["server_saturated_tuned"]["autotune_wall_ms"] = dict(zip(["4", "8", "16", "32"], cand))
+    out["server_saturated_tuned"]["autotune_wall_ms"] = dict(zip([str(v) for v in TUNE_SLOTS], cand))
     r_plain = out["plain_saturated"]["requests_per_s"]
     for name, f in (("0.7x", 0.7), ("2x", 2.0)):
         rate = f * r_plain
@@ -366,7 +366,7 @@ def batched_bench(ctx):
     measured beside it."""
     import torch
     from paper_2511_13905_amd import inputs as I
-    from paper_2511_13905_amd.api import make_params, problem_struct, _Keep, batch_autotune
+    from paper_2511_13905_amd.api import TUNE_SLOTS, make_params, problem_struct, _Keep, batch_autotune
     pool = [I.compliance_3d(s) for s in range(8)]
     dev = [(torch.from_numpy(p.y).to("cuda:0"), torch.from_numpy(p.A).to("cuda:0")) for p in pool]
     nreq = 64
@@ -414,7 +414,7 @@ def batched_bench(ctx):
     out = {"workload": f"{nreq} x project, single compliance row, 256x128x128 (n=4194304), float32, "
                        "8 distinct inputs, all submitted at once",
            "passes_mean": sum(per) / nreq,
-           "autotune": {"candidates_slots": [4, 8, 16, 32], "wall_ms": cand_ms, "chosen": [slots, wg],
+           "autotune": {"candidates_slots": TUNE_SLOTS, "wall_ms": cand_ms, "chosen": [slots, wg],
                         "tuning_s": tune_s},
            "default_shape": default}
     out.update(tuned)

@@ -325,7 +325,7 @@ int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot);
  * `count` float32 requests, taken round-robin from samples[0..nsamples-1]
  * (distinct instances, so that inputs are not all served from cache), all
  * submitted at once, through executors of PGDTO_TUNE_SHAPES candidate
- * shapes: 4, 8, 16, 32 slots, each with the co-resident workgroups split
+ * shapes: 4, 8, 16, 32, 64 slots, each with the co-resident workgroups split
  * evenly; every shape runs twice and its faster run counts.  Writes the
  * fastest shape to *slots, *wg_per_slot (for pgdto_batch_cfg.max_slots and
  * wg_per_slot) and, when times_ms is not NULL, the wall time of each
@@ -335,7 +335,7 @@ int pgdto_batch_shape(pgdto_batch* b, int32_t* slots, int32_t* wg_per_slot);
  * is written (by several requests at once, with the same values) and their
  * free_mask is ignored.  PGDTO_ERR_ARG for a bad argument or a float64
  * sample; otherwise the first error of a request. */
-#define PGDTO_TUNE_SHAPES 4
+#define PGDTO_TUNE_SHAPES 5
 int pgdto_batch_autotune(pgdto_ctx* ctx, const pgdto_problem* samples, int nsamples,
                          const pgdto_params* params, int count, int32_t* slots, int32_t* wg_per_slot,
                          float* times_ms);

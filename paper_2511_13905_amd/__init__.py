@@ -11,10 +11,10 @@ __all__ = ["inputs", "api", "native"]
 
 def __getattr__(name):
     # the binding needs torch and the built library; load it on first use
+    # (import_module, not "from . import": that form asks this hook again)
+    import importlib
     if name == "api":
-        from . import api
-        return api
+        return importlib.import_module(__name__ + ".api")
     if name == "native":
-        from . import _native
-        return _native
+        return importlib.import_module(__name__ + "._native")
     raise AttributeError(name)

@@ -353,7 +353,8 @@ class Batch:
             pass
 
 
-TUNE_SHAPES = 4
+TUNE_SHAPES = 5                                   # PGDTO_TUNE_SHAPES
+TUNE_SLOTS = [4 << c for c in range(TUNE_SHAPES)]   # slot counts of the candidates
 
 
 def batch_autotune(ctx: Context, problems, count: int = 64, params=None):

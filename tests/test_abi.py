@@ -185,3 +185,11 @@ def test_product_package_does_not_import_the_oracle():
             "assert not bad, bad")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
+
+
+def test_tune_shape_count_matches_header():
+    """The binding sizes the autotuner's timing array from the header's
+    PGDTO_TUNE_SHAPES."""
+    from paper_2511_13905_amd import api
+    m = re.search(r"#define\s+PGDTO_TUNE_SHAPES\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == api.TUNE_SHAPES == len(api.TUNE_SLOTS)

@@ -99,7 +99,7 @@ def test_server_shape(ctx):
 
 
 def test_batch_autotune_picks_fastest_shape(ctx):
-    from paper_2511_13905_amd.api import Batch, aligned_rows, batch_autotune
+    from paper_2511_13905_amd.api import TUNE_SLOTS, Batch, aligned_rows, batch_autotune
     reqs = [I.compliance_3d(s, n=200003) for s in range(4)]
     say("batch autotune", [p.n for p in reqs])
     probs, xs = [], []
@@ -109,7 +109,7 @@ def test_batch_autotune_picks_fastest_shape(ctx):
         xs.append(x)
     torch.cuda.synchronize()
     (s, w), times = batch_autotune(ctx, probs, count=16)
-    cand = [4, 8, 16, 32]
+    cand = TUNE_SLOTS
     assert len(times) == len(cand) and all(np.isfinite(t) and t > 0 for t in times), times
     assert s in cand and times[cand.index(s)] == min(times)
     B = Batch(ctx, max_slots=s, wg_per_slot=w, slots_only=True)
