@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 3      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0 */
+#define PGDTO_VERSION 3      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
