@@ -342,21 +342,26 @@ def test_warm_start_equality_rows(ctx, case):
     assert r["lam"][0] == pytest.approx(ref.lam[0], rel=1e-6)
 
 
-def test_graph_replay_matches_eager(ctx):
+@pytest.mark.parametrize("warm", [False, True])
+def test_graph_replay_matches_eager(ctx, warm):
     """One-instance launches captured in a HIP graph (two projections, masks
     included) and replayed three times, with eager launches on the same
-    context between replays: every replay gives the bits of eager calls."""
+    context between replays: every replay gives the bits of eager calls.
+    warm: both start from the same lambda0 (1.01 x the oracle's multipliers),
+    which the captured launch holds in its kernel argument."""
     from paper_2511_13905_amd.api import result_from_bytes, result_nbytes
     probs = [I.compliance_3d(6, n=100003), I.volume_com(1, grid=(64, 32))]
-    say("graph replay", [p.n for p in probs])
+    lam0s = [[max(0.0, 1.01 * float(v)) for v in orc(p).lam] if warm else None for p in probs]
+    say("graph replay", "warm" if warm else "cold", [p.n for p in probs])
     dev_in = [(dev(p.y), dev(p.A)) for p in probs]
     xs = [torch.empty(p.n, dtype=torch.float32, device="cuda:0") for p in probs]
     ms = [torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0") for p in probs]
     rs = [torch.zeros(result_nbytes(), dtype=torch.uint8, device="cuda:0") for _ in probs]
 
     def enqueue():
-        for p, (y, A), x, m, r in zip(probs, dev_in, xs, ms, rs):
-            ctx.project_async(p.kind, y, A, p.b, p.lo, p.hi, r, C=p.C, offsets=p.offsets, x=x, free_mask=m)
+        for p, (y, A), x, m, r, l0 in zip(probs, dev_in, xs, ms, rs, lam0s):
+            ctx.project_async(p.kind, y, A, p.b, p.lo, p.hi, r, C=p.C, offsets=p.offsets, x=x, free_mask=m,
+                              lam0=l0)
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -369,9 +374,9 @@ def test_graph_replay_matches_eager(ctx):
         enqueue()
     torch.cuda.synchronize()
     eager = []
-    for p, (y, A) in zip(probs, dev_in):
+    for p, (y, A), l0 in zip(probs, dev_in, lam0s):
         m = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
-        x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=m)
+        x, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=m, lam0=l0)
         torch.cuda.synchronize()
         eager.append((x.cpu().numpy(), m.cpu().numpy(), r))
     other = I.multi_material(5, fields=2, n_per=20011)
