@@ -77,10 +77,11 @@ def pgd_step(kind, rho, rho_prev, grad, grad_prev, d_prev, A, g, G, t, lo, hi,
     rho~ = rho_t + omega alpha_t d_t, rho_{t+1} = projection of rho~, and the
     relative-change stop test.  All arithmetic in float64.
 
-    ``stream_dtype``: the precision in which rho~ is stored before it is
-    projected (the paper does not fix one).  With float32 streams rho~ is a
-    float32 array like any other input of the projection, so it is rounded
-    once here; everything else stays float64."""
+    ``stream_dtype``: the precision in which rho~ and rho_{t+1} are stored
+    (the paper does not fix one).  With float32 streams rho~ is a float32
+    array like any other input of the projection, so it is rounded once here,
+    and the stop test is taken on rho_{t+1} rounded to float32, the iterate
+    the next step starts from; everything else stays float64."""
     p = p or PgdParams()
     f64 = lambda v: np.asarray(v, dtype=np.float64)
     rho, rho_prev, grad, grad_prev, d_prev = map(f64, (rho, rho_prev, grad, grad_prev, d_prev))
@@ -101,9 +102,14 @@ def pgd_step(kind, rho, rho_prev, grad, grad_prev, d_prev, A, g, G, t, lo, hi,
         arho = np.array([fsum(Ad[j] * rho) for j in range(Ad.shape[0])])
     b = G - g + arho
     res = project(kind, rho_t, A, b, lo, hi, C, offsets)
-    diff = res.x - rho
+    # the stop test measures rho_{t+1} as it is stored: the next iterate is the
+    # stored array, so with float32 streams x is rounded once before the test
+    x_st = res.x
+    if stream_dtype is not None and np.dtype(stream_dtype) != np.float64:
+        x_st = res.x.astype(stream_dtype).astype(np.float64)
+    diff = x_st - rho
     num = math.sqrt(fsum(diff * diff))
-    den = math.sqrt(fsum(res.x * res.x))
+    den = math.sqrt(fsum(x_st * x_st))
     rel = num / den if den > 0.0 else math.inf
     return {"alpha": alpha, "beta": beta, "used_fallback": used_fb, "d": d, "rho_tilde": rho_t,
-            "b": b, "proj": res, "x": res.x, "rel_change": rel, "converged": rel <= p.tol}
+            "b": b, "proj": res, "x": res.x, "x_stored": x_st, "rel_change": rel, "converged": rel <= p.tol}

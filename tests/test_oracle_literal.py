@@ -105,3 +105,108 @@ def test_pgd_step_rhs_matches_paper_form():
     a = A[0]
     ghat = st.G[0] - st.g[0] + out["alpha"] * P.fsum(st.grad.astype(float) * a)
     assert out["b"][0] - P.fsum(a * out["rho_tilde"]) == pytest.approx(ghat, rel=1e-9, abs=1e-6)
+
+
+# ------------------------------------------------------------------ hand-worked Algorithm 3 steps
+
+def _golden_pgd():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "pgd_step_hand_worked.json")
+    with open(path) as f:
+        return json.load(f)["cases"]
+
+
+def _run_golden(c, pgd_fn=pgd_step):
+    p = PgdParams(cg_rule=c["cg_rule"], omega=c["omega"], tol=c["tol"])
+    sd = np.float32 if c.get("stream_dtype") == "float32" else None
+    A = np.asarray(c["A"], dtype=np.float64)
+    C = math.inf if c["C"] == "inf" else float(c["C"])
+    f = lambda k: np.asarray(c[k], dtype=np.float64)
+    return pgd_fn(c["kind"], f("rho"), f("rho_prev"), f("grad"), f("grad_prev"), f("d_prev"), A,
+                  c["g"], c["G"], c["t"], c["lo"], c["hi"], C=C, p=p, stream_dtype=sd)
+
+
+@pytest.mark.parametrize("name", [c["name"] for c in _golden_pgd()])
+def test_pgd_step_hand_worked(name):
+    """One body of Algorithm 3 against values worked by hand with exact
+    fractions (tests/golden/pgd_step_hand_worked.json): the spectral step and
+    the fallback after warm-up, beta of eq. (CG) in both rules with beta != 0,
+    omega != 1 (Sec. 3.4.3), b, the projection and the stop test."""
+    c = next(c for c in _golden_pgd() if c["name"] == name)
+    out = _run_golden(c)
+    assert out["used_fallback"] == c["used_fallback"]
+    assert out["alpha"] == pytest.approx(c["alpha"], rel=1e-13)
+    assert out["beta"] == pytest.approx(c["beta"], rel=1e-13, abs=1e-300)
+    np.testing.assert_allclose(out["d"], c["d"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(out["rho_tilde"], c["rho_tilde"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(out["b"], c["b"], rtol=1e-13)
+    assert out["proj"].outcome == [c["outcome"]]
+    np.testing.assert_allclose(out["proj"].lam, c["lam"], rtol=1e-6 if c["lam"][0] < 1e-6 else 1e-12, atol=0)
+    np.testing.assert_allclose(out["x"], c["x"], rtol=1e-12, atol=0)
+    if "x_stored" in c:
+        assert np.array_equal(out["x_stored"], np.asarray(c["x_stored"]))
+    if c["rel_change"] == 0.0:
+        assert out["rel_change"] == 0.0
+    else:
+        assert out["rel_change"] == pytest.approx(c["rel_change"], rel=1e-12)
+    assert out["converged"] == c["converged"]
+    if "rel_change_unrounded" in c:
+        # the same step with float64 storage measures the unrounded iterate
+        c64 = dict(c)
+        c64.pop("stream_dtype")
+        o64 = _run_golden(c64)
+        assert o64["rel_change"] == pytest.approx(c["rel_change_unrounded"], rel=1e-6)
+
+
+def test_pgd_step_planted_mistakes_fail_the_hand_worked_pins(monkeypatch):
+    """Plausible slips in the Algorithm 3 body (a flipped beta sign, omega
+    dropped, the stop test on the unrounded iterate, FR and PR+ swapped, the
+    fallback ignored after warm-up) each change a value the hand-worked cases
+    fix."""
+    import oracle.pgd as PG
+    cases = {c["name"]: c for c in _golden_pgd()}
+
+    def fails(name, **patch):
+        with monkeypatch.context() as mp:
+            for k, v in patch.items():
+                mp.setattr(PG, k, v)
+            c = cases[name]
+            out = _run_golden(c, PG.pgd_step)
+            ok = (np.allclose(out["d"], c["d"], rtol=1e-12, atol=0)
+                  and np.allclose(out["rho_tilde"], c["rho_tilde"], rtol=1e-12, atol=0)
+                  and np.allclose(out["x"], c["x"], rtol=1e-12, atol=0)
+                  and out["alpha"] == pytest.approx(c["alpha"], rel=1e-13)
+                  and (out["rel_change"] == c["rel_change"] if c["rel_change"] == 0.0
+                       else out["rel_change"] == pytest.approx(c["rel_change"], rel=1e-12)))
+            return not ok
+
+    real_beta = PG.cg_beta
+    assert fails("spectral_step_pr_plus_half_omega", cg_beta=lambda *a, **k: -real_beta(*a, **k))
+    swap = {"pr+": "fr", "fr": "pr+", "none": "none"}
+    assert fails("fallback_after_warmup_fletcher_reeves_active_row",
+                 cg_beta=lambda g, gp, t, rule="pr+": real_beta(g, gp, t, swap[rule]))
+    assert fails("spectral_step_pr_plus_half_omega",
+                 PgdParams=PgdParams, pgd_step=_omega_dropped(PG))
+    real_step = PG.step_size
+    assert fails("fallback_after_warmup_fletcher_reeves_active_row",
+                 step_size=lambda rho, rp, gr, gp, g, G, t, p: real_step(rho, rp, gr, gp, g, G, min(t, 1), p))
+    real_np = PG.np
+
+    class NoRound:                      # the stop test on the unrounded iterate
+        def __getattr__(self, k):
+            return getattr(real_np, k)
+
+        @staticmethod
+        def dtype(v):
+            return real_np.dtype(real_np.float64)
+    assert fails("stop_test_on_the_stored_iterate", np=NoRound())
+
+
+def _omega_dropped(PG):
+    real = PG.pgd_step
+
+    def wrapped(*a, p=None, **k):
+        q = PgdParams(**{**p.__dict__, "omega": 1.0})
+        return real(*a, p=q, **k)
+    return wrapped
