@@ -57,7 +57,8 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 3      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes */
+#define PGDTO_VERSION 4      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
+                                4: pgdto_result.lambda_err, x_err */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
@@ -175,9 +176,28 @@ typedef struct {
   double resid[PGDTO_MAX_BLOCKS];   /* a_j.x - b_j with x as stored          */
   double slack[PGDTO_MAX_BLOCKS];   /* kappa lam_j (eq. s_y_robust)          */
   int32_t row_outcome[PGDTO_MAX_BLOCKS];
-  double res_inf;        /* max_j scaled KKT residual at exit                */
-  double lambda_width;   /* final bracket width (1-D searches, max)          */
+  double res_inf;        /* max_j scaled KKT residual of x as stored:
+                            |h_j| / sigma_j for rows with lambda_j != 0 and
+                            equality rows, max(h_j, 0) / sigma_j otherwise,
+                            h_j = a_j.x - b_j - kappa lambda_j, sigma_j =
+                            sum_i |a_ji| max(|lo|, |hi|)                   */
+  double lambda_width;   /* width of the final bracket of the 1-D searches
+                            (max over rows; a root of the computed dual
+                            function lies in it), 0 when no search ran      */
   double kappa;          /* regularization used: 2/C, or the automatic value */
+  /* Stated error of the result against the exact solution of the problem
+   * as given (Theorems 1 and 2: x and lambda are unique when kappa > 0).
+   * lambda_err[j]: 2 |h_j| / slope_j at the last evaluated point of a 1-D
+   * search (capped by its bracket width), or 2 |Delta_j| for the Newton
+   * step that the float64 factor of (A D A^T + kappa I) on the active rows
+   * gives at the returned multipliers, plus 16 float64 rounding units of
+   * |lambda_j| and of sigma_j / slope_j; INFINITY when the slope is zero (a
+   * flat stretch of the dual, kappa = 0: lambda is not unique there, x is).
+   * x_err: sum_j max_i |a_ji| lambda_err[j] (max over blocks for
+   * independent blocks) plus half a unit in the last place of the stream
+   * dtype at max(|lo|, |hi|): a bound on max_i |x_i - x*_i|. */
+  double lambda_err[PGDTO_MAX_BLOCKS];
+  double x_err;
 } pgdto_result;
 
 typedef struct {

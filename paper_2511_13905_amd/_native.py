@@ -51,7 +51,8 @@ class Result(C.Structure):
                 ("m", C.c_int32), ("error", C.c_int32), ("n_free", C.c_int64),
                 ("lambda_", C.c_double * MAX_BLOCKS), ("resid", C.c_double * MAX_BLOCKS),
                 ("slack", C.c_double * MAX_BLOCKS), ("row_outcome", C.c_int32 * MAX_BLOCKS),
-                ("res_inf", C.c_double), ("lambda_width", C.c_double), ("kappa", C.c_double)]
+                ("res_inf", C.c_double), ("lambda_width", C.c_double), ("kappa", C.c_double),
+                ("lambda_err", C.c_double * MAX_BLOCKS), ("x_err", C.c_double)]
 
     def to_dict(self) -> dict:
         m = self.m
@@ -62,7 +63,8 @@ class Result(C.Structure):
                 "lam": list(self.lambda_[:m]), "resid": list(self.resid[:m]),
                 "slack": list(self.slack[:m]),
                 "row_outcome": [OUTCOME_NAMES.get(o, str(o)) for o in self.row_outcome[:m]],
-                "res_inf": self.res_inf, "lambda_width": self.lambda_width, "kappa": self.kappa}
+                "res_inf": self.res_inf, "lambda_width": self.lambda_width, "kappa": self.kappa,
+                "lambda_err": list(self.lambda_err[:m]), "x_err": self.x_err}
 
 
 class PgdArgs(C.Structure):

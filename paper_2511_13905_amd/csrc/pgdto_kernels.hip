@@ -500,6 +500,8 @@ struct Search {
   double slo[PGDTO_MAX_BLOCKS], shi[PGDTO_MAX_BLOCKS];
   double lam[PGDTO_MAX_BLOCKS], scale[PGDTO_MAX_BLOCKS], width[PGDTO_MAX_BLOCKS];
   double ssat[PGDTO_MAX_BLOCKS];
+  double err[PGDTO_MAX_BLOCKS];     // stated |lam - lam*| at exit (before the rounding allowance)
+  double slope[PGDTO_MAX_BLOCKS];   // slope of the dual function at exit (0: unknown or flat)
   double trial[PGDTO_MAX_BLOCKS][NT];
   int32_t state[PGDTO_MAX_BLOCKS], outcome[PGDTO_MAX_BLOCKS], npass[PGDTO_MAX_BLOCKS];
   int32_t shrunk[PGDTO_MAX_BLOCKS];
@@ -552,6 +554,8 @@ __device__ __forceinline__ bool search_init(Search& S, int s, double f0, double 
   S.scale[s] = scale;
   S.ssat[s] = ssat;
   S.shrunk[s] = 1;
+  S.err[s] = 0.0;                     // the exits below are exact up to rounding
+  S.slope[s] = s0;
   if (!(f0 > 0.0)) {                  // delta(0) feasible: y* = 0 (Alg. 1, first branch)
     S.lam[s] = 0.0;
     S.outcome[s] = PGDTO_INACTIVE;
@@ -563,6 +567,7 @@ __device__ __forceinline__ bool search_init(Search& S, int s, double f0, double 
   if (fhi >= 0.0) {
     // no sign change inside the bracket: every element with a_i != 0 is
     // saturated from bp on; phi is linear there with slope -kappa.
+    S.slope[s] = kappa;
     if (kappa > 0.0) {
       S.lam[s] = bp + fhi / kappa;
       S.outcome[s] = (ssat - b > 0.0) ? PGDTO_INFEASIBLE : PGDTO_CONVERGED;
@@ -600,14 +605,14 @@ __device__ __forceinline__ void search_update(Search& S, int s, double f0sum, do
   const double ssum[NT] = {s0sum, s1sum};
   const double eps = tol_n * S.scale[s];
   const double w0 = S.hi[s] - S.lo[s];
-  double best = NAN, bestf = INFINITY;
+  double best = NAN, bestf = INFINITY, bests = 0.0;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const double lt = S.trial[s][t];
     if (!(lt == lt)) continue;
     const double f = fsum[t] - b - kappa * lt;
     const double sl = ssum[t] + kappa;
-    if (mode != PGDTO_SEARCH_BISECT && fabs(f) <= eps && fabs(f) < bestf) { best = lt; bestf = fabs(f); }
+    if (mode != PGDTO_SEARCH_BISECT && fabs(f) <= eps && fabs(f) < bestf) { best = lt; bestf = fabs(f); bests = sl; }
     if (f > 0.0 && lt > S.lo[s]) { S.lo[s] = lt; S.flo[s] = f; S.slo[s] = sl; }
     else if (f <= 0.0 && lt < S.hi[s]) { S.hi[s] = lt; S.fhi[s] = f; S.shi[s] = sl; }
   }
@@ -616,8 +621,12 @@ __device__ __forceinline__ void search_update(Search& S, int s, double f0sum, do
   const double w = hi - lo;
   S.shrunk[s] = (w <= 0.5 * w0) ? 1 : 0;
   if (best == best) {
+    // the root lies in the bracket, of which `best` is an end; on the
+    // linear piece through `best` it is |f| / slope away (twice that stated)
     S.lam[s] = best;
-    S.width[s] = 0.0;
+    S.width[s] = w;
+    S.slope[s] = bests;
+    S.err[s] = (bestf == 0.0) ? 0.0 : (bests > 0.0 ? fmin(w, 2.0 * bestf / bests) : w);
     S.outcome[s] = PGDTO_CONVERGED;
     S.state[s] = SEG_DONE;
     return;
@@ -630,6 +639,8 @@ __device__ __forceinline__ void search_update(Search& S, int s, double f0sum, do
     if (!(l >= lo && l <= hi)) l = 0.5 * (lo + hi);
     S.lam[s] = l;
     S.width[s] = w;
+    S.slope[s] = (S.fhi[s] == 0.0) ? S.shi[s] : 0.5 * (S.slo[s] + S.shi[s]);
+    S.err[s] = (S.fhi[s] == 0.0) ? 0.0 : w;
     S.outcome[s] = (S.npass[s] >= max_pass && w > wtol && S.fhi[s] != 0.0) ? PGDTO_MAXITER : PGDTO_CONVERGED;
     S.state[s] = SEG_DONE;
     return;
@@ -648,6 +659,26 @@ __device__ __forceinline__ double auto_kappa(double tau, const double* bp, int s
     if (isfinite(v) && v > mx) mx = v;
   }
   return mx > 0.0 ? tau / mx : 0.0;
+}
+
+// Stated error of a multiplier: the estimate `est` of |lam - lam*| plus 16
+// float64 rounding units of |lam| and of sigma / slope (the shift of the root
+// that a rounding-level error of the sums moves it by); a zero slope (a flat
+// stretch of the dual at kappa = 0, where lam is not unique) states INFINITY
+// unless the estimate is exact.
+__device__ __forceinline__ double lam_error(double lam, double est, double sigma, double slope) {
+  constexpr double U16 = 16.0 * 2.220446049250313e-16;
+  if (!(est == est)) return INFINITY;
+  if (!(slope > 0.0)) return (est == 0.0) ? U16 * fabs(lam) : INFINITY;
+  return est + U16 * (fabs(lam) + sigma / slope);
+}
+
+// Half a unit in the last place of the stream dtype at v >= 0: the rounding
+// of a value of magnitude at most v when x is stored.
+__device__ __forceinline__ double half_ulp(double v, bool f32) {
+  int e = 0;
+  (void)frexp(v, &e);                   // v = f 2^e, f in [0.5, 1)
+  return ldexp(1.0, e - (f32 ? 25 : 54));
 }
 
 // Control parameters, copied once into LDS so that no reference to the
@@ -707,7 +738,8 @@ __device__ __forceinline__ void pgd_scalars(const Desc& d, const double* v, PgdS
 // lockstep passes (Alg. 1; Sec. 3.2.2 for independent blocks).
 
 struct Sh1D {
-  double tot[PGDTO_MAX_BLOCKS * 8];
+  double tot[PGDTO_MAX_BLOCKS * 9];
+  double amax[PGDTO_MAX_BLOCKS];  // max_i |a_i| per segment (zero pass)
   double red[NWAVE * BLOCK];
   double bs[PGDTO_MAX_BLOCKS];
   double sg[PGDTO_MAX_BLOCKS];    // -1: an equality row searched in the opposite direction (lam < 0)
@@ -742,6 +774,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     sh.sg[s] = 1.0;
     sh.S.state[s] = SEG_DONE; sh.S.lam[s] = 0.0; sh.S.npass[s] = 0; sh.S.width[s] = 0.0;
     sh.S.outcome[s] = PGDTO_INACTIVE; sh.S.scale[s] = 1.0; sh.S.ssat[s] = 0.0;
+    sh.S.err[s] = 0.0; sh.S.slope[s] = 0.0; sh.amax[s] = 0.0;
   }
   __syncthreads();
 
@@ -866,14 +899,15 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         // rows held at equality (Sec. 3.2) also need the bracket of the
         // opposite direction: the EQ instantiation adds its two sums
         auto zero_tile = [&]() __attribute__((always_inline)) {
-          constexpr int NZ = EQ ? 8 : 6;
+          constexpr int NZ = EQ ? 9 : 7;
+          constexpr int ZA = NZ - 1;         // max |a|
           nv = NZ;
-          maxmask = EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2);
+          maxmask = (EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2)) | (1ull << ZA);
           // lam = 0: a.clip(y), slope, largest breakpoint, saturated sum, sum |a|,
-          // non-finite count [, largest opposite breakpoint, sum a . other bound]
+          // non-finite count [, largest opposite breakpoint, sum a . other bound], max |a|
           double acc[NZ];
 #pragma unroll
-          for (int v = 0; v < NZ; ++v) acc[v] = (v == 2 || v == 6) ? -INFINITY : 0.0;
+          for (int v = 0; v < NZ; ++v) acc[v] = (v == 2 || (EQ && v == 6)) ? -INFINITY : 0.0;
           // lam = 0: a.clip(y), slope, largest breakpoint, saturated sum, sum |a|, non-finite count
           auto zero_elem = [&](double y, double av) __attribute__((always_inline)) {
             const double x0 = clampd(y, lo, hi);
@@ -893,6 +927,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               }
             }
             acc[4] += fabs(av);
+            acc[ZA] = fmax(acc[ZA], fabs(av));
             if (!isfinite(y) || !isfinite(av)) acc[5] += 1.0;
           };
           if (tile == wid && g.nsweep <= RS) {
@@ -1169,7 +1204,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
       }
     }
-    if (ph == PH_ZERO) { nv = EQ ? 8 : 6; maxmask = EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2); }
+    if (ph == PH_ZERO) { nv = EQ ? 9 : 7; maxmask = (EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2)) | (1ull << (nv - 1)); }
     else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
     else { nv = 4; maxmask = 0; }
 
@@ -1180,10 +1215,11 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 
     // ---------------- control (identical in every workgroup)
     if (ph == PH_ZERO) {
-      constexpr int zs = EQ ? 8 : 6;
+      constexpr int zs = EQ ? 9 : 7;
       if (d.auto_tau > 0.0) kappa = auto_kappa(d.auto_tau, &sh.tot[2], zs, d.nseg);
       for (int s = tid; s < d.nseg; s += BLOCK) {
         const double* t = &sh.tot[s * zs];
+        sh.amax[s] = t[zs - 1];
         double scale = t[4] * fmax(fabs(lo), fabs(hi));
         if (!(scale > 0.0)) scale = 1.0;
         const bool eq = EQ && ((d.eq_mask >> s) & 1ull);
@@ -1191,6 +1227,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         if (t[5] > 0.0) {
           sh.S.lam[s] = 0.0; sh.S.outcome[s] = PGDTO_NONFINITE; sh.S.state[s] = SEG_DONE;
           sh.S.npass[s] = 0; sh.S.width[s] = 0.0; sh.S.scale[s] = scale;
+          sh.S.err[s] = NAN; sh.S.slope[s] = 0.0;
         } else if (eq && f0 < 0.0) {
           // equality row below its target (Sec. 3.2): the opposite
           // inequality (-a).x <= -b is the active one; search it for
@@ -1233,19 +1270,31 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         for (int s = tid; s < d.nseg; s += BLOCK) {
           const double lam_s = (EQ ? sh.sg[s] : 1.0) * sh.S.lam[s];
+          const double r = sh.tot[s * 4 + 0] - sh.bs[s];
           R->lambda[s] = lam_s;
-          R->resid[s] = sh.tot[s * 4 + 0] - sh.bs[s];
+          R->resid[s] = r;
           R->slack[s] = kappa * lam_s;
           R->row_outcome[s] = sh.S.outcome[s];
+          const double le = lam_error(lam_s, sh.S.err[s], sh.S.scale[s], sh.S.slope[s]);
+          R->lambda_err[s] = le;
+          sh.red[PGDTO_MAX_BLOCKS + s] = le;
+          // scaled KKT residual of the stored x (equality rows: always active)
+          const double h = r - kappa * lam_s;
+          const bool act = (lam_s != 0.0) || (EQ && ((d.eq_mask >> s) & 1ull));
+          sh.red[s] = (act ? fabs(h) : fmax(h, 0.0)) / sh.S.scale[s];
         }
+        __syncthreads();
         if (tid == 0) {
           int worst = PGDTO_INACTIVE, anyact = 0, np = 0;
-          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0;
+          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0, rmax = 0.0, xerr = 0.0;
           for (int s = 0; s < d.nseg; ++s) {
             if (severity(sh.S.outcome[s]) > severity(worst)) worst = sh.S.outcome[s];
             anyact |= (sh.S.outcome[s] != PGDTO_INACTIVE);
             np = max(np, sh.S.npass[s]);
             wmax = fmax(wmax, sh.S.width[s]);
+            rmax = fmax(rmax, sh.red[s]);
+            // blocks are disjoint: the element error is the largest block's
+            xerr = fmax(xerr, sh.amax[s] * sh.red[PGDTO_MAX_BLOCKS + s]);
             nfree += sh.tot[s * 4 + 1];
             diff2 += sh.tot[s * 4 + 2];
             xx += sh.tot[s * 4 + 3];
@@ -1259,9 +1308,10 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
           R->iters_ls = 0;
           R->m = d.nseg;
           R->n_free = (int64_t)nfree;
-          R->res_inf = 0.0;
+          R->res_inf = rmax;
           R->lambda_width = wmax;
           R->kappa = kappa;
+          R->x_err = xerr + half_ulp(fmax(fabs(lo), fabs(hi)), sizeof(T) == 4);
           if (d.pgd) {
             pgdto_pgd_out* P = (pgdto_pgd_out*)d.result;
             P->alpha = sh.pg.alpha;
@@ -1391,7 +1441,7 @@ template <int M> struct CN {
   static constexpr int NJ = M * (M + 1) / 2;
   static constexpr bool FUSE = (M <= 3);
   static constexpr int NV_R = 7 + M;
-  static constexpr int NV_ZERO = 5 * M + 1;
+  static constexpr int NV_ZERO = 6 * M + 1;      // ..., non-finite count, then max |a_j| per row
   static constexpr int NV_S1 = 2 * NT * M;
   static constexpr int NV_NEWTON = M + NJ;
   static constexpr int NV_CHECK = M * M + (FUSE ? NV_NEWTON : 0);
@@ -1419,6 +1469,10 @@ struct ShC {
   PgdScalars pg;
   CtlParams P;
   double lamf[PGDTO_MAX_M];    // multiplier used by the final pass
+  double lerr[PGDTO_MAX_M];    // stated |lam - lam*| estimate at exit (before the rounding allowance)
+  double lslope[PGDTO_MAX_M];  // diagonal of (A D A^T + kappa I) or the 1-D slope at exit
+  double amax[PGDTO_MAX_M];    // max_i |a_ji| (zero pass)
+  double asum[PGDTO_MAX_M];    // sum_i |a_ji| (zero pass)
   double res_inf;
   int32_t phase, abort_flag, passes, path, outcome, nonfinite, s1passes, pad;
 };
@@ -1556,12 +1610,6 @@ __device__ __forceinline__ int newton_accept(ShC& sh, const double (&lam)[M], co
   const int eq = sh.P.eq;
   const double res = kkt_residual<M>(h, lam, scale, eq);
   sh.res_inf = res;
-  if (res <= tol_n || it >= max_newton) {
-    sh.outcome = res <= tol_n ? PGDTO_CONVERGED : PGDTO_MAXITER;
-#pragma unroll
-    for (int j = 0; j < M; ++j) sh.lamf[j] = lam[j];
-    return PH_FINAL;
-  }
   double phi[M], delta[M];
   bool act[M];
   ncp<M>(h, J, lam, kappa, ncp_mode, eq, phi, act);
@@ -1569,6 +1617,19 @@ __device__ __forceinline__ int newton_accept(ShC& sh, const double (&lam)[M], co
 #pragma unroll
   for (int j = 0; j < M; ++j) p2 += phi[j] * phi[j];
   newton_direction<M>(h, J, lam, kappa, act, phi, ncp_mode, delta);
+  if (res <= tol_n || it >= max_newton) {
+    sh.outcome = res <= tol_n ? PGDTO_CONVERGED : PGDTO_MAXITER;
+    // stated error: the step the float64 factor gives at the returned
+    // multipliers (exact when the free pattern at the solution is the
+    // current one), doubled
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      sh.lamf[j] = lam[j];
+      sh.lerr[j] = 2.0 * fabs(delta[j]);
+      sh.lslope[j] = J[j * PGDTO_MAX_M + j] + kappa;
+    }
+    return PH_FINAL;
+  }
   N.phi2 = p2;
   N.M0 = 0.5 * p2;
   N.gamma = 1.0;
@@ -1679,6 +1740,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
   }
   if (tid < M) {
     sh.bs[tid] = d.b[tid]; sh.lamf[tid] = 0.0; sh.N.lam1[tid] = 0.0;
+    sh.lerr[tid] = 0.0; sh.lslope[tid] = 0.0; sh.amax[tid] = 0.0;
     sh.S.state[tid] = SEG_DONE; sh.S.lam[tid] = 0.0; sh.S.npass[tid] = 0; sh.S.width[tid] = 0.0;
     sh.S.outcome[tid] = PGDTO_INACTIVE; sh.S.scale[tid] = 1.0; sh.S.ssat[tid] = 0.0;
   }
@@ -1706,7 +1768,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
     uint64_t maxmask = 0;
     switch (ph) {
       case PH_PGD_R: nv = C::NV_R; maxmask = 1ull << 6; break;
-      case PH_ZERO: nv = C::NV_ZERO; maxmask = ((1ull << M) - 1) << (2 * M); break;
+      case PH_ZERO: nv = C::NV_ZERO; maxmask = (((1ull << M) - 1) << (2 * M)) | (((1ull << M) - 1) << (5 * M + 1)); break;
       case PH_STAGE1: nv = C::NV_S1; break;
       case PH_CHECK: nv = C::NV_CHECK; break;
       case PH_NEWTON: nv = C::NV_NEWTON; break;
@@ -1796,6 +1858,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
                 acc[3 * M + j] = fma(av, bound, acc[3 * M + j]);
               }
               acc[4 * M + j] += fabs(av);
+              acc[5 * M + 1 + j] = fmax(acc[5 * M + 1 + j], fabs(av));
               bad |= !isfinite(av);
             }
             if (bad) acc[5 * M] += 1.0;
@@ -2014,6 +2077,9 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         double scale = t[4 * M + j] * fmax(fabs(lo), fabs(hi));
         if (!(scale > 0.0)) scale = 1.0;
         sh.S.scale[j] = scale;
+        sh.amax[j] = t[5 * M + 1 + j];
+        sh.asum[j] = t[4 * M + j];
+        sh.S.slope[j] = t[M + j] + kappa;
         sh.N.h0[j] = t[j] - sh.bs[j];
         sh.S.ssat[j] = t[3 * M + j];
         if (d.stage1 && !d.eq_mask && !d.warm && t[5 * M] == 0.0) {
@@ -2082,7 +2148,11 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           if (ok) found = j;
         }
         if (found >= 0) {
-          for (int j = 0; j < M; ++j) sh.lamf[j] = (j == found) ? sh.N.lam1[j] : 0.0;
+          for (int j = 0; j < M; ++j) {
+            sh.lamf[j] = (j == found) ? sh.N.lam1[j] : 0.0;
+            sh.lerr[j] = (j == found) ? sh.S.err[j] : 0.0;
+            sh.lslope[j] = sh.S.slope[j];
+          }
           sh.path = 2;
           sh.outcome = PGDTO_CONVERGED;
           sh.phase = PH_FINAL;
@@ -2126,18 +2196,37 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         if (tid < M) {
           const int j = tid;
-          R->lambda[j] = sh.lamf[j];
+          const bool eqj = (d.eq_mask >> j) & 1ull;
+          const double lamj = sh.lamf[j];
+          R->lambda[j] = lamj;
           R->resid[j] = t[j] - sh.bs[j];
-          R->slack[j] = kappa * sh.lamf[j];
-          int o = sh.lamf[j] > 0.0 ? PGDTO_CONVERGED : PGDTO_INACTIVE;
+          R->slack[j] = kappa * lamj;
+          // equality rows are always active (Sec. 3.2): converged with a
+          // multiplier of either sign, infeasible when b_j lies outside the
+          // range of a_j.x over the box [ssat_j, ssat_j + sum |a_j| (hi - lo)]
+          int o = (eqj || lamj > 0.0) ? PGDTO_CONVERGED : PGDTO_INACTIVE;
           if (sh.S.ssat[j] - sh.bs[j] > 0.0) o = PGDTO_INFEASIBLE;
+          if (eqj && sh.bs[j] - (sh.S.ssat[j] + sh.asum[j] * (hi - lo)) > 0.0) o = PGDTO_INFEASIBLE;
           if (sh.outcome == PGDTO_MAXITER || sh.outcome == PGDTO_NONFINITE) o = sh.outcome;
           R->row_outcome[j] = o;
+          const double le = sh.nonfinite ? INFINITY : lam_error(lamj, sh.lerr[j], sh.S.scale[j], sh.lslope[j]);
+          R->lambda_err[j] = le;
+          const double h = t[j] - sh.bs[j] - kappa * lamj;
+          // per-row values for the summary below, through LDS
+          sh.red[j] = ((eqj || lamj != 0.0) ? fabs(h) : fmax(h, 0.0)) / sh.S.scale[j];
+          sh.red[PGDTO_MAX_M + j] = le;
+          sh.red[2 * PGDTO_MAX_M + j] = (double)o;
         }
+        __syncthreads();
         if (tid == 0) {
           int worst = sh.outcome;
-          for (int j = 0; j < M; ++j)
-            if (sh.S.ssat[j] - sh.bs[j] > 0.0 && severity(PGDTO_INFEASIBLE) > severity(worst)) worst = PGDTO_INFEASIBLE;
+          double rmax = 0.0, xerr = 0.0;
+          for (int j = 0; j < M; ++j) {
+            if ((int)sh.red[2 * PGDTO_MAX_M + j] == PGDTO_INFEASIBLE && severity(PGDTO_INFEASIBLE) > severity(worst))
+              worst = PGDTO_INFEASIBLE;
+            rmax = fmax(rmax, sh.red[j]);
+            xerr += sh.amax[j] * sh.red[PGDTO_MAX_M + j];
+          }
           R->outcome = worst;
           R->error = 0;
           R->path = sh.path;
@@ -2149,7 +2238,8 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           R->iters_ls = ls_total;
           R->m = M;
           R->n_free = (int64_t)t[M];
-          R->res_inf = sh.res_inf;
+          R->res_inf = rmax;
+          R->x_err = xerr + half_ulp(fmax(fabs(lo), fabs(hi)), sizeof(T) == 4);
           double wmax = 0.0;
           for (int j = 0; j < M; ++j) wmax = fmax(wmax, sh.S.width[j]);
           R->lambda_width = wmax;
