@@ -57,8 +57,8 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 4      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
-                                4: pgdto_result.lambda_err, x_err */
+#define PGDTO_VERSION 5      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
+                                4: pgdto_result.lambda_err, x_err; 5: pgdto_project_noalloc */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
@@ -72,7 +72,9 @@ typedef enum {
   PGDTO_ERR_UNKNOWN_TICKET = -4,
   PGDTO_ERR_TIMEOUT = -5,      /* a device-side wait ran past its bound    */
   PGDTO_ERR_BUSY = -6,         /* batch: queue full                        */
-  PGDTO_ERR_CANCELLED = -7     /* batch: destroyed before the request ran  */
+  PGDTO_ERR_CANCELLED = -7,    /* batch: destroyed before the request ran  */
+  PGDTO_ERR_SCRATCH = -8       /* pgdto_project_noalloc: the problem needs
+                                  more workspace than the static array holds */
 } pgdto_status;
 
 typedef enum {
@@ -277,6 +279,29 @@ int pgdto_project(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params*
  * streams). */
 int pgdto_project_async(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params,
                         pgdto_result* result_dev, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * projection of pgdto_project_async with no context.  Its workspace
+ * (per-tile partial sums, barrier and arrival-door words;
+ * PGDTO_NOALLOC_SCRATCH_BYTES) is a static array of the library in device
+ * memory, one copy per GPU, held until the process ends.  The call allocates
+ * nothing: no hipMalloc, hipFree or allocating library routine.  It runs on
+ * the calling thread's current HIP device; `stream` must belong to it.  The
+ * first call on a device looks up that device's copy of the array and clears
+ * it with one small kernel on `stream` (enqueued before the solve); every
+ * later call enqueues the solve kernel only, like pgdto_project_async.  The
+ * result struct is written to `result_dev` (device memory, caller-owned);
+ * params may be NULL.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap in time on one GPU race
+ * (issue them on one stream, or order their streams).  The array holds the
+ * tile table of every problem the ABI accepts (at most 704 tiles of at most
+ * 112 partial values); a problem beyond it returns PGDTO_ERR_SCRATCH before
+ * anything is launched.  Argument errors: PGDTO_ERR_ARG, as for
+ * pgdto_project_async. */
+#define PGDTO_NOALLOC_SCRATCH_BYTES 1466752
+int pgdto_project_noalloc(const pgdto_problem* prob, const pgdto_params* params, pgdto_result* result_dev,
+                          void* stream);
 
 /* One body of Algorithm 3 (step size, direction, rho~, projection, stop test),
  * one launch; waits and fills *out.  The _async form writes the

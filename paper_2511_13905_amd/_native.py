@@ -17,7 +17,9 @@ MAX_BLOCKS = 64
 
 # enums (pgdto.h)
 OK, PENDING, QUEUED = 0, 1, 2
-ERR_ARG, ERR_HIP, ERR_NOMEM, ERR_UNKNOWN_TICKET, ERR_TIMEOUT, ERR_BUSY, ERR_CANCELLED = -1, -2, -3, -4, -5, -6, -7
+ERR_ARG, ERR_HIP, ERR_NOMEM, ERR_UNKNOWN_TICKET, ERR_TIMEOUT, ERR_BUSY, ERR_CANCELLED, ERR_SCRATCH = (
+    -1, -2, -3, -4, -5, -6, -7, -8)
+NOALLOC_SCRATCH_BYTES = 1466752
 CONVERGED, INACTIVE, INFEASIBLE, MAXITER, NONFINITE = 0, 1, 2, 3, 4
 OUTCOME_NAMES = {0: "converged", 1: "inactive", 2: "infeasible", 3: "maxiter", 4: "nonfinite"}
 F32, F64 = 0, 1
@@ -104,6 +106,7 @@ SIGNATURES = {
     "pgdto_ctx_last_launch": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pgdto_project": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), C.POINTER(Result), _VP]),
     "pgdto_project_async": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP]),
+    "pgdto_project_noalloc": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, _VP]),
     "pgdto_pgd_step": (C.c_int, [_VP, C.POINTER(PgdArgs), C.POINTER(Params), C.POINTER(PgdOut), _VP]),
     "pgdto_pgd_step_async": (C.c_int, [_VP, C.POINTER(PgdArgs), C.POINTER(Params), _VP, _VP]),
     "pgdto_batch_create": (C.c_int, [_VP, C.POINTER(BatchCfg), C.POINTER(_VP)]),

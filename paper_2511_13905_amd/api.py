@@ -240,6 +240,25 @@ class Context:
         return x
 
 
+def project_noalloc(kind, y, A, b, lo, hi, result_buf: torch.Tensor, C=math.inf, offsets=None, x=None,
+                    free_mask=None, params=None, stream=None, eq=None, lam0=None):
+    """pgdto_project_noalloc: pgdto_project_async with no context (the library's
+    static device scratch array is the workspace; the call allocates nothing
+    on the device: x must be given, A rows already 16-byte aligned).  Runs on the current device; calls
+    that overlap in time on one GPU race.  The result struct lands in
+    result_buf (uint8 device tensor of at least sizeof(pgdto_result) bytes)."""
+    if x is None:
+        raise ValueError("project_noalloc: pass the output x (the call allocates nothing)")
+    keep = _Keep()
+    s, x, _A = problem_struct(kind, y, A, b, lo, hi, C, offsets, x, free_mask, keep, copy_ok=False, eq=eq,
+                              lam0=lam0)
+    p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+    dev = y.device.index if y.device.index is not None else torch.cuda.current_device()
+    st = N.lib().pgdto_project_noalloc(C_byref(s), C_byref(p), result_buf.data_ptr(), _stream(dev, stream))
+    _check(st, "pgdto_project_noalloc")
+    return x
+
+
 def C_byref(obj):
     return C.byref(obj)
 

@@ -22,7 +22,7 @@ struct pgdto_ctx {
   int autotune = 0;
   std::unordered_map<uint64_t, int> tuned_grid;
   int forced_grid = 0;                        // set while a candidate is timed
-  uint64_t door_wait = 3000;                  // arrival-door wait of one-instance launches (100 MHz ticks)
+  uint64_t door_wait = pgdto::DOOR_WAIT_DEFAULT;   // arrival-door wait of one-instance launches (100 MHz ticks)
 };
 
 namespace pgdto {

@@ -61,6 +61,7 @@ extern "C" const char* pgdto_status_string(int s) {
     case PGDTO_ERR_TIMEOUT: return "device wait timed out";
     case PGDTO_ERR_BUSY: return "queue full";
     case PGDTO_ERR_CANCELLED: return "cancelled";
+    case PGDTO_ERR_SCRATCH: return "problem exceeds the static scratch array";
     default: return "unknown status";
   }
 }

@@ -28,6 +28,10 @@ constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + (size_t)NREP * REP_WORDS + 16 
 // workgroup gives up, flags PGDTO_ERR_TIMEOUT and leaves the kernel.
 constexpr uint32_t SPIN_LIMIT = 1u << 20;
 
+// Longest wait of the arrival door of one-instance launches for the whole
+// grid, in ticks of the 100 MHz clock (30 us).
+constexpr uint64_t DOOR_WAIT_DEFAULT = 3000;
+
 // Everything one launch needs, passed by value as the kernel argument (the
 // multi-instance server kernel reads the same struct from device memory).
 struct Desc {

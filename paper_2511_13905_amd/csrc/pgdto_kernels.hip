@@ -22,9 +22,11 @@
 // and is summed in float.
 
 #include "pgdto_internal.h"
+#include "pgdto_ctx.h"
 
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 namespace pgdto {
@@ -2481,4 +2483,94 @@ hipError_t launch_mark_error(void* result, int is_pgd, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ static scratch
+// Workspace of pgdto_project_noalloc: the per-tile partial sums followed by
+// the barrier and arrival-door words, laid out as in a context.  One copy per
+// GPU, resident from module load to process end.  In host code `scratch`
+// names a host-side stand-in; its device address on the current GPU comes
+// from hipGetSymbolAddress, once per device, and only that address is ever
+// passed to a kernel.
+constexpr size_t NOALLOC_WORDS = (size_t)PART_DOUBLES + SYNC_WORDS;
+static_assert(NOALLOC_WORDS * sizeof(uint64_t) == PGDTO_NOALLOC_SCRATCH_BYTES, "scratch size in pgdto.h");
+static __device__ __align__(256) uint64_t scratch[NOALLOC_WORDS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+struct NoallocDevice {
+  uint64_t* ptr = nullptr;                  // device address of `scratch` on this GPU
+  int cap[2][2][PGDTO_MAX_M + 1] = {};      // co-resident workgroups per kernel
+};
+static NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+static std::mutex g_noalloc_mu;
+
+// Clears the scratch words (the first call on a device).  A kernel rather
+// than a memset, so that a call captured into a HIP graph records a kernel node.
+__global__ __launch_bounds__(256) void k_clear_words(uint64_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
 }  // namespace pgdto
+
+extern "C" int pgdto_project_noalloc(const pgdto_problem* prob, const pgdto_params* params, pgdto_result* result_dev,
+                                     void* stream) {
+  using namespace pgdto;
+  if (!prob || !result_dev) return PGDTO_ERR_ARG;
+  pgdto_params tmp;
+  if (!params) {
+    pgdto_params_default(&tmp);
+    params = &tmp;
+  }
+  Desc d;
+  const int st = build_desc(prob, params, true, d);
+  if (st != PGDTO_OK) return st;
+  // the partial-sum table holds TILES_PAD tiles of VMAX values (sized for
+  // PGDTO_MAX_M coupled rows), the totals at most TOT_MAX values
+  if (d.ntiles > TILES_PAD || (d.kind == PGDTO_COUPLED && d.m > PGDTO_MAX_M) || d.nseg * 9 > TOT_MAX)
+    return PGDTO_ERR_SCRATCH;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return PGDTO_ERR_HIP;
+  const hipStream_t s = (hipStream_t)stream;
+  uint64_t* ws = nullptr;
+  bool first = false;
+  int grid = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoallocDevice& D = g_noalloc[dev];
+    if (!D.ptr) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PGDTO_ERR_HIP;
+      D.ptr = (uint64_t*)p;
+      first = true;
+    }
+    ws = D.ptr;
+    const int ki = d.kind == PGDTO_COUPLED ? 1 : 0;
+    int& cap = D.cap[ki][d.dtype][ki ? d.m : 0];
+    if (cap == 0) cap = max_coresident(d.kind, d.dtype, d.m, dev);
+    if (cap <= 0) return PGDTO_ERR_HIP;
+    grid = d.ntiles < cap ? d.ntiles : cap;
+    if (grid < 1) grid = 1;
+  }
+  if (first) {
+    hipLaunchKernelGGL(k_clear_words, dim3(256), dim3(256), 0, s, ws, NOALLOC_WORDS);
+    if (hipGetLastError() != hipSuccess) {
+      std::lock_guard<std::mutex> lock(g_noalloc_mu);
+      g_noalloc[dev].ptr = nullptr;        // clear again on the next call
+      return PGDTO_ERR_HIP;
+    }
+  }
+  d.part = (double*)ws;
+  d.sync = ws + PART_DOUBLES;
+  d.epoch0 = 0;                            // replaced on the device by the door's generation
+  d.trace = nullptr;
+  d.result = result_dev;
+  d.pgd = 0;
+  d.wg_base = 0;
+  d.wg_count = grid;
+  d.door_wait = DOOR_WAIT_DEFAULT;
+  if (launch_solve(d, grid, s, false) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)launch_mark_error(result_dev, 0, s);
+    return PGDTO_ERR_HIP;
+  }
+  return PGDTO_OK;
+}
