@@ -1,17 +1,20 @@
 """Benchmark of the projection hot path on one MI355X.
 
-Default workload: one Algorithm 3 step (step size, conjugate direction,
-rho~, single-row projection, stop test) on the 256x128x128 single-constraint
-case (n = 4,194,304, float32 streams), i.e. one pgdto_pgd_step launch per
-step.  Inputs are synthetic (seeded), resident in HBM before timing; steps
-rotate over several independent instances whose combined footprint exceeds
-the 256 MB Infinity Cache, so every step reads its inputs from HBM.
+Default workload (one step = one launch): one Algorithm 3 step (step size,
+conjugate direction, rho~, single-row projection, stop test) on each of 16
+distinct instances of the 256x128x128 single-constraint case (n = 4,194,304
+each, float32 streams), solved together by one pgdto_pgd_step_batch_async
+launch.  The 16 instances (1.9 GB) are far larger than the 256 MB Infinity
+Cache, so every pass reads its inputs from HBM.  Inputs are synthetic
+(seeded) and resident in HBM before timing.
 
 Prints one JSON line: the metric, throughput and latency of the timed steps,
-the roofline of the kernel (algorithmic bytes per launch over the launch time
-from HIP events, measured HBM traffic when the kernel source matches the
-profiled one), the CPU oracle's rate and the error against it, and the
-served-stream and batched measurements.
+the roofline of the batch kernel (algorithmic bytes per launch over the
+launch time from HIP events on the launch stream, and the HBM traffic that
+rocprofv3 counters measured for the same kernel source), the one-instance
+launch (warm and after a 1 GB cache flush), the CPU oracle's rate on the
+host (one thread and a process pool) and the error against it, and the
+served-stream and server-route batch measurements.
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -27,24 +31,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+ESZ = 4                    # float32 streams
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pgd_compliance",
                     choices=["pgd_compliance", "project_compliance", "multimaterial", "volcom"])
-    ap.add_argument("--instances", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16, help="distinct instances per launch")
+    ap.add_argument("--slots", type=int, default=0, help="slots of the batch launch (0: pick by a short sweep)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream and batched measurements")
-    ap.add_argument("--autotune", type=int, default=1,
-                    help="grid autotuner of the one-instance launch (1: on, 0: off)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream and server-route batch")
+    ap.add_argument("--no-single", action="store_true", help="skip the one-instance launch measurements")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-pool", type=int, default=128,
                     help="distinct request instances the served stream cycles through")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes that generate the inputs (1 under a profiler)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -55,14 +62,7 @@ def parse():
 # scaled by the same counters on a plain 1 GiB copy.  Reported only while the
 # kernel source is the one that was measured (sha256 of the HIP file).
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
-MEASURED_TRAFFIC = {
-    # profiles/k_solve_1d_f32_pgd_compliance_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "4ac8e5ad421ab964", "bytes_per_launch": 193654286,
-                       "read": 158753290, "written": 34900996},
-    # profiles/k_solve_1d_f32_project_compliance_hbm_traffic.md
-    "project_compliance": {"kernel_sha": "4ac8e5ad421ab964", "bytes_per_launch": 54191356,
-                           "read": 36152900, "written": 18038456},
-}
+MEASURED_TRAFFIC = {}
 
 
 def kernel_sha():
@@ -75,7 +75,7 @@ def traffic_for(workload):
     m = MEASURED_TRAFFIC.get(workload)
     if not m or m["kernel_sha"] != kernel_sha():
         return None
-    return m["bytes_per_launch"]
+    return m
 
 
 def copy_calibration():
@@ -91,6 +91,59 @@ def copy_calibration():
                                            "kernel": "elementwise mul by 1.0 (float32)"}}), flush=True)
 
 
+# ---------------------------------------------------------------- inputs
+def _gen_pgd(seed):
+    from paper_2511_13905_amd import inputs as I
+    return I.pgd_compliance_3d(seed, t=60)
+
+
+def _gen_proj(wl_seed):
+    from paper_2511_13905_amd import inputs as I
+    wl, seed = wl_seed
+    return {"project_compliance": I.compliance_3d, "multimaterial": I.multi_material,
+            "volcom": I.volume_com}[wl](seed)
+
+
+def generate(fn, args, workers):
+    """Seeded instances, generated in a process pool (before the GPU is touched)."""
+    if workers <= 1 or len(args) <= 1:
+        return [fn(a) for a in args]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(workers, len(args))) as pool:
+        return pool.map(fn, args)
+
+
+def host_cpu():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+# ---------------------------------------------------------------- byte model
+def pgd_bytes(n, passes):
+    """Algorithmic bytes of one pgd_step (float32 streams): pass R reads
+    rho, rho_prev, grad, grad_prev, a; the zero pass reads rho, grad, d, a and
+    writes d, rho~; each search pass reads rho~, a; the final pass reads rho~,
+    a, rho and writes x."""
+    return n * ESZ * (5 + 6 + 2 * (passes - 3) + 4)
+
+
+def proj_bytes(n, rows, passes):
+    """Every pass reads y and the rows; the final pass also writes x."""
+    return passes * n * ESZ * (1 + rows) + n * ESZ
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -100,10 +153,26 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
+    cpu = host_cpu()
+    workers = max(1, min(args.gen_workers, cpu["usable_cpus"]))
+    wl = args.workload
+    B = max(1, args.batch)
+    t_gen = time.perf_counter()
+    if wl == "pgd_compliance":
+        states = generate(_gen_pgd, list(range(B)), workers)
+    else:
+        states = generate(_gen_proj, [(wl, s) for s in range(B)], workers)
+    t_gen = time.perf_counter() - t_gen
+
+    # the CPU oracle runs before the GPU is initialised (its process pool forks)
+    cpu_line, refs = (None, [])
+    if not args.no_cpu_baseline:
+        cpu_line, refs = cpu_baseline(wl, states, args.cpu_seconds, workers, cpu)
+
     import numpy as np
     import torch
     from paper_2511_13905_amd import inputs as I
-    from paper_2511_13905_amd.api import Context, result_from_bytes, result_nbytes
+    from paper_2511_13905_amd.api import Context, aligned_rows, close_all, result_from_bytes, result_nbytes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -113,109 +182,101 @@ def main():
     def T(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
-    R = max(1, args.instances)
-    insts = []
-    wl = args.workload
-    if wl == "pgd_compliance":
-        for s in range(R):
-            st = I.pgd_compliance_3d(s, t=60)
-            insts.append(dict(A=T(st.problem.A), rho=T(st.rho), rho_prev=T(st.rho_prev), grad=T(st.grad),
-                              grad_prev=T(st.grad_prev), d=T(st.d_prev), g=st.g, G=st.G, t=st.t,
-                              x=torch.empty_like(T(st.rho)), st=st))
-        n = insts[0]["rho"].numel()
-        m = 1
-        kind = "single"
-        dtype = "f32"
-        workload = "pgd_step, single linearized compliance row, 256x128x128 grid (n=4194304), float32 streams"
-    else:
-        gen = {"project_compliance": lambda s: I.compliance_3d(s),
-               "multimaterial": lambda s: I.multi_material(s),
-               "volcom": lambda s: I.volume_com(s)}[wl]
-        for s in range(R):
-            p = gen(s)
-            insts.append(dict(p=p, y=T(p.y), A=T(p.A), x=torch.empty(p.n, dtype=torch.float32, device=dev)))
-        p0 = insts[0]["p"]
-        n, m, kind = p0.n, p0.m, p0.kind
-        dtype = "f32"
-        workload = {"project_compliance": "project, single compliance row, 256x128x128 (n=4194304), float32",
-                    "multimaterial": "project, 4 independent volume blocks of 524288 (n=2097152), float32",
-                    "volcom": "project, volume + centre-of-mass m=5 coupled, 192x96x96 (n=1769472), float32, "
-                              "even seeds feasible / odd seeds infeasible"}[wl]
-
     is_pgd = wl == "pgd_compliance"
+    if is_pgd:
+        insts = [dict(kind="single", A=T(st.problem.A), rho=T(st.rho), rho_prev=T(st.rho_prev), grad=T(st.grad),
+                      grad_prev=T(st.grad_prev), d=T(st.d_prev), g=st.g, G=st.G, t=st.t, lo=I.LO, hi=I.HI)
+                 for st in states]
+        for it in insts:
+            it["x"] = torch.empty_like(it["rho"])
+        n, m, rows = insts[0]["rho"].numel(), 1, 1
+        workload = (f"pgd_step on {B} distinct instances per launch, single linearized compliance row, "
+                    "256x128x128 grid (n=4194304 each), float32 streams")
+    else:
+        insts = []
+        for p in states:
+            A = T(p.A)
+            if p.kind != "independent":
+                A = aligned_rows(A)
+            insts.append(dict(p=p, y=T(p.y), A=A, x=torch.empty(p.n, dtype=torch.float32, device=dev)))
+        p0 = states[0]
+        n, m = p0.n, p0.m
+        rows = m if p0.kind == "coupled" else 1
+        workload = {"project_compliance": "project, single compliance row, 256x128x128 (n=4194304)",
+                    "multimaterial": "project, 4 independent volume blocks of 524288 (n=2097152)",
+                    "volcom": "project, volume + centre-of-mass m=5 coupled, 192x96x96 (n=1769472), "
+                              "even seeds feasible / odd seeds infeasible"}[wl]
+        workload = f"{workload} on {B} distinct instances per launch, float32"
     nres = result_nbytes(pgd=is_pgd)
-    res_bufs = [torch.zeros(nres, dtype=torch.uint8, device=dev) for _ in range(R)]
+    res_buf = torch.zeros(nres * B, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
 
-    def launch(i):
-        it = insts[i % R]
+    def launch(slots):
         if is_pgd:
-            ctx.pgd_step_async("single", it["A"], it["rho"], it["rho_prev"], it["grad"], it["grad_prev"], it["d"],
-                               it["g"], it["G"], it["t"], I.LO, I.HI, res_bufs[i % R], x=it["x"])
+            ctx.pgd_step_batch_async(insts, res_buf, slots=slots)
         else:
-            p = it["p"]
-            ctx.project_async(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, res_bufs[i % R], C=p.C,
-                              offsets=p.offsets, x=it["x"])
+            ctx.project_batch_async([(it["p"].kind, it["y"], it["A"], it["p"].b, it["p"].lo, it["p"].hi, it["p"].C,
+                                      it["p"].offsets, it["x"]) for it in insts], res_buf, slots=slots)
 
-    if args.autotune:
-        # one blocking projection per shape class lets the context pick its grid
-        ctx.autotune(1)
-        it = insts[0]
-        if is_pgd:
-            st0 = it["st"]
-            ctx.project("single", it["rho"], it["A"], [float(st0.G[0] - st0.g[0]) + 0.0], I.LO, I.HI)
-        else:
-            p = it["p"]
-            ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C, offsets=p.offsets)
+    def timed(slots, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            launch(slots)
+        e1.record(stream)
         torch.cuda.synchronize()
-    for i in range(args.warmup):
-        launch(i)
+        return e0.elapsed_time(e1) / k
+
+    # slot count of the batch launch: a short sweep (each candidate warmed once)
+    sweep = {}
+    if args.slots > 0:
+        slots = args.slots
+    else:
+        for s in (4, 8, 16):
+            if s > B:
+                continue
+            timed(s, 1)
+            sweep[str(s)] = timed(s, 3)
+        slots = int(min(sweep, key=sweep.get)) if sweep else 0
+    for _ in range(args.warmup):
+        launch(slots)
     torch.cuda.synchronize()
 
     # per-launch kernel durations (HIP events on the launch stream)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record(stream)
     for i in range(args.steps):
         evs[i][0].record(stream)
-        launch(i)
+        launch(slots)
         evs[i][1].record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    total_ms = t0.elapsed_time(t1)
-    per = [a.elapsed_time(b) for a, b in evs]
-    ms_step = total_ms / args.steps
+    ms_step = t0.elapsed_time(t1) / args.steps
+    per = sorted(a.elapsed_time(b) for a, b in evs)
     kern_ms = sum(per) / len(per)
-    per_sorted = sorted(per)
-    p50 = per_sorted[len(per) // 2]
-    p99 = per_sorted[min(len(per) - 1, int(math.ceil(0.99 * len(per))) - 1)]
+    grid, tiles = ctx.last_launch()
 
-    # passes taken (algorithmic bytes follow the algorithm's own pass count)
-    results = [result_from_bytes(b, pgd=is_pgd) for b in res_bufs]
+    results = [result_from_bytes(res_buf[i * nres:(i + 1) * nres], pgd=is_pgd) for i in range(B)]
     proj = [r["proj"] if is_pgd else r for r in results]
-    passes = sum(r["passes"] for r in proj) / len(proj)
+    passes = [r["passes"] for r in proj]
     errors = [r["error"] for r in proj]
-    esz = 4
     if is_pgd:
-        # pass R: rho, rho_prev, grad, grad_prev, a; pass D+0: rho, grad, d, a read, d, rho~ written;
-        # each search pass: rho~, a; final: rho~, a, rho read, x written
-        search_passes = passes - 3
-        bytes_launch = n * esz * (5 + 6 + 2 * search_passes + 4)
-        compulsory = n * esz * (6 + 2)
+        bytes_launch = sum(pgd_bytes(n, p) for p in passes)
+        compulsory = B * n * ESZ * (6 + 2)
     else:
-        rows = m if kind == "coupled" else 1
-        per_pass = n * esz * (1 + rows)
-        bytes_launch = passes * per_pass + n * esz          # final pass also writes x
-        compulsory = n * esz * (1 + rows + 1)
+        bytes_launch = sum(proj_bytes(st.n, rows, p) for st, p in zip(states, passes))
+        compulsory = sum(st.n * ESZ * (rows + 2) for st in states)
+    elems = B * n if is_pgd else sum(st.n for st in states)
     achieved = bytes_launch / (kern_ms * 1e-3)
-    value = n / (ms_step * 1e-3)
-
+    tr = traffic_for(wl)
     line = {
         "metric": "projected elements/s and % HBM roofline; p50/p99 batched projection latency",
-        "value": value,
+        "value": elems / (ms_step * 1e-3),
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -224,28 +285,108 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "instances_rotated": R, "passes_per_launch": passes,
-                   "latency_ms": {"p50": p50, "p99": p99}, "wall_s": wall, "device_errors": errors,
-                   "kernel_sha": kernel_sha(), "grid_workgroups": ctx.last_launch()[0],
-                   "tiles": ctx.last_launch()[1], "autotune": bool(args.autotune)},
+        "config": {"workload": workload, "instances_per_launch": B, "elements_per_launch": elems,
+                   "slots": slots, "slot_sweep_ms": sweep, "grid_workgroups": grid, "tiles_per_instance": tiles,
+                   "passes_per_instance": {"mean": sum(passes) / B, "min": min(passes), "max": max(passes)},
+                   "latency_ms": {"p50": per[len(per) // 2],
+                                  "p99": per[min(len(per) - 1, int(math.ceil(0.99 * len(per))) - 1)]},
+                   "wall_s": wall, "device_errors": sorted(set(errors)), "kernel_sha": kernel_sha(),
+                   "input_generation_s": t_gen},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": traffic_for(wl),
-                     "bytes_per_launch": bytes_launch, "kernel_ms": kern_ms},
+                     "frac": achieved / HBM_PEAK, "traffic": tr["bytes_per_launch"] if tr else None,
+                     "kernel": "k_batch", "bytes_per_launch": bytes_launch, "kernel_ms": kern_ms},
         "roofline_compulsory": {"bytes": compulsory, "achieved": compulsory / (kern_ms * 1e-3) / 1e9,
                                 "unit": "GB/s", "frac": compulsory / (kern_ms * 1e-3) / HBM_PEAK},
     }
+    if tr:
+        line["roofline"]["traffic_read"] = tr["read"]
+        line["roofline"]["traffic_written"] = tr["written"]
+        line["roofline"]["traffic_frac"] = tr["bytes_per_launch"] / (kern_ms * 1e-3) / HBM_PEAK
+    if not args.no_single:
+        line["single_instance"] = single_bench(ctx, insts, is_pgd, n, rows, args)
     if not args.no_serve:
         line["serving"] = serve_bench(ctx, args)
-        line["batched"] = batched_bench(ctx)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"], refs = cpu_baseline(wl, insts, args.cpu_seconds, n)
-        line["oracle_error"] = oracle_error(ctx, wl, insts, refs)
-    ctx.close()
+        if wl == "project_compliance":
+            line["server_batch"] = server_batch_bench(ctx, insts, args)
+    if cpu_line is not None:
+        line["cpu_baseline"] = cpu_line
+        line["oracle_error"] = oracle_error(ctx, wl, states, insts, refs)
+    # explicit teardown: executors and contexts, then the device, before exit
+    close_all()
+    del insts, res_buf
+    torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
 
 
+# ---------------------------------------------------------------- one instance
+def single_bench(ctx, insts, is_pgd, n, rows, args):
+    """One-instance launches (pgdto_pgd_step_async / pgdto_project_async),
+    four instances in turn: warm (back to back) and cold (each after a 1 GB
+    streaming copy that evicts the Infinity Cache and L2)."""
+    import torch
+    from paper_2511_13905_amd import inputs as I
+    from paper_2511_13905_amd.api import result_from_bytes, result_nbytes
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    R = min(4, len(insts))
+    nres = result_nbytes(pgd=is_pgd)
+    bufs = [torch.zeros(nres, dtype=torch.uint8, device=dev) for _ in range(R)]
+
+    def launch(i):
+        it = insts[i % R]
+        if is_pgd:
+            ctx.pgd_step_async("single", it["A"], it["rho"], it["rho_prev"], it["grad"], it["grad_prev"], it["d"],
+                               it["g"], it["G"], it["t"], I.LO, I.HI, bufs[i % R], x=it["x"])
+        else:
+            p = it["p"]
+            ctx.project_async(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, bufs[i % R], C=p.C, offsets=p.offsets,
+                              x=it["x"])
+
+    for i in range(4):
+        launch(i)
+    torch.cuda.synchronize()
+    K = max(8, args.steps)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for i in range(K):
+        evs[i][0].record(stream)
+        launch(i)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    warm = sorted(a.elapsed_time(b) for a, b in evs)
+    res = [result_from_bytes(b, pgd=is_pgd) for b in bufs]
+    passes = [(r["proj"] if is_pgd else r)["passes"] for r in res]
+    # cold: a 1 GB copy before each launch
+    flush_src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    flush_dst = torch.empty_like(flush_src)
+    cold = []
+    for i in range(8):
+        flush_dst.copy_(flush_src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        launch(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    cold.sort()
+    del flush_src, flush_dst
+    mean_ms = sum(warm) / len(warm)
+    mean_passes = sum(passes) / len(passes)
+    alg = pgd_bytes(n, mean_passes) if is_pgd else proj_bytes(n, rows, mean_passes)
+    return {"launch": "pgdto_pgd_step_async" if is_pgd else "pgdto_project_async",
+            "instances_rotated": R, "passes_mean": mean_passes, "grid_tiles": list(ctx.last_launch()),
+            "warm_ms": {"mean": mean_ms, "p50": warm[len(warm) // 2], "p99": warm[-1]},
+            "cold_ms": {"p50": cold[len(cold) // 2], "max": cold[-1],
+                        "flush": "1 GB device copy before each launch"},
+            "elements_per_s": n / (mean_ms * 1e-3),
+            "algorithmic_GBps": alg / (mean_ms * 1e-3) / 1e9,
+            "algorithmic_frac": alg / (mean_ms * 1e-3) / HBM_PEAK,
+            "note": "one instance is latency-bound: its first tiles stay in registers across passes and "
+                    "the per-pass grid synchronisation dominates; the HBM fraction is that of the batch"}
+
+
+# ---------------------------------------------------------------- serving
 def _pctl(v, q):
     v = sorted(v)
     return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
@@ -357,130 +498,157 @@ def serve_bench(ctx, args):
     return out
 
 
-def batched_bench(ctx):
-    """64 projections of the 256x128x128 single-row problem (8 distinct
-    instances, distinct outputs) through the persistent executor, all
-    submitted at once: algorithmic bytes of every pass over wall time.  The
-    executor shape (slots x workgroups per slot) comes from
-    pgdto_batch_autotune on the same instances; the default serving shape is
-    measured beside it."""
+def server_batch_bench(ctx, insts, args):
+    """The persistent executor (server route) on 64 projections of the
+    256x128x128 single-row problem, all submitted at once: 4 device copies of
+    each of the 16 distinct instances, so no two requests read the same
+    memory; algorithmic bytes of every pass over the wall time."""
     import torch
-    from paper_2511_13905_amd import inputs as I
-    from paper_2511_13905_amd.api import TUNE_SLOTS, make_params, problem_struct, _Keep, batch_autotune
-    pool = [I.compliance_3d(s) for s in range(8)]
-    dev = [(torch.from_numpy(p.y).to("cuda:0"), torch.from_numpy(p.A).to("cuda:0")) for p in pool]
-    nreq = 64
+    from paper_2511_13905_amd.api import make_params, problem_struct, _Keep
     keep = _Keep()
-    structs, xs = [], []
-    for i in range(nreq):
-        p = pool[i % 8]
-        y, A = dev[i % 8]
-        x = torch.empty(p.n, dtype=torch.float32, device="cuda:0")
+    structs, hold, ns, per = [], [], [], []
+    params = make_params()
+    passes = {}
+    for i in range(64):
+        it = insts[i % len(insts)]
+        p = it["p"]
+        y, A = it["y"].clone(), it["A"].clone()
+        x = torch.empty_like(y)
+        hold.append((y, A, x))
         st, _, _ = problem_struct(p.kind, y, A, p.b, p.lo, p.hi, p.C, None, x, None, keep, copy_ok=False)
         structs.append(st)
-        xs.append(x)
+        ns.append(p.n)
+        if i < len(insts):
+            _, r = ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C)
+            passes[i] = r["passes"]
+        per.append(proj_bytes(p.n, 1, passes[i % len(insts)]))
     torch.cuda.synchronize()
-    params = make_params()
-    tune_x = [torch.empty(p.n, dtype=torch.float32, device="cuda:0") for p in pool]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    (slots, wg), cand_ms = batch_autotune(
-        ctx, [(p.kind, y, A, p.b, p.lo, p.hi, p.C, None, x) for p, (y, A), x in zip(pool, dev, tune_x)],
-        count=nreq, params=params)
-    tune_s = time.perf_counter() - t0
-    n = pool[0].n
-    passes = []
-    for p, (y, A) in zip(pool, dev):
-        _, r = ctx.project(p.kind, y, A, p.b, p.lo, p.hi, p.C)
-        passes.append(r["passes"])
-    per = [passes[i % 8] for i in range(nreq)]
-    alg = sum(pp * n * 8 + n * 4 for pp in per)
-
-    def measure(max_slots, wg_per_slot):
-        _run_stream(ctx, structs[:16], params, max_slots, [0.0] * 16, wg_per_slot)     # warm-up
+    alg = sum(per)
+    out = {"workload": "64 x project, 256x128x128 single row (n=4194304), float32, 16 distinct instances in "
+                       "4 device copies each, all submitted at once"}
+    for name, slots in (("shape_8x32", 8), ("shape_32x8", 32)):
+        _run_stream(ctx, structs[:16], params, slots, [0.0] * 16)
         best = None
-        for _ in range(3):
-            times, status, shape = _run_stream(ctx, structs, params, max_slots, [0.0] * nreq, wg_per_slot)
+        for _ in range(2):
+            times, status, shape = _run_stream(ctx, structs, params, slots, [0.0] * 64)
             wall = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
             if best is None or wall < best[0]:
                 best = (wall, status, shape)
         wall, status, shape = best
-        return {"errors": sum(1 for x in status if x != 0), "wall_s": wall, "projections_per_s": nreq / wall,
-                "elements_per_s": nreq * n / wall, "algorithmic_GBps": alg / wall / 1e9,
-                "hbm_frac": alg / wall / HBM_PEAK, "server_shape": {"slots": shape[0], "wg_per_slot": shape[1]}}
-
-    tuned = measure(slots, wg)
-    default = measure(0, 0)
-    out = {"workload": f"{nreq} x project, single compliance row, 256x128x128 (n=4194304), float32, "
-                       "8 distinct inputs, all submitted at once",
-           "passes_mean": sum(per) / nreq,
-           "autotune": {"candidates_slots": TUNE_SLOTS, "wall_ms": cand_ms, "chosen": [slots, wg],
-                        "tuning_s": tune_s},
-           "default_shape": default}
-    out.update(tuned)
+        out[name] = {"errors": sum(1 for x in status if x != 0), "wall_s": wall, "projections_per_s": 64 / wall,
+                     "elements_per_s": sum(ns) / wall, "algorithmic_GBps": alg / wall / 1e9,
+                     "hbm_frac": alg / wall / HBM_PEAK, "server_shape": {"slots": shape[0], "wg_per_slot": shape[1]}}
+    del hold
     return out
 
 
-def cpu_baseline(wl, insts, budget_s, n):
-    """The CPU oracle, as it stands, on a bounded sample of the same workload."""
+# ---------------------------------------------------------------- CPU oracle
+_POOL_STATES = None
+
+
+def _oracle_one(wl, st):
     import numpy as np
     import oracle
     from paper_2511_13905_amd import inputs as I
-    done = 0
+    if wl == "pgd_compliance":
+        return oracle.pgd_step("single", st.rho, st.rho_prev, st.grad, st.grad_prev, st.d_prev, st.problem.A, st.g,
+                               st.G, st.t, I.LO, I.HI, stream_dtype=np.float32)
+    return oracle.project(st.kind, st.y, st.A, st.b, st.lo, st.hi, st.C, st.offsets)
+
+
+def _pool_task(args):
+    wl, i = args
+    t = time.perf_counter()
+    _oracle_one(wl, _POOL_STATES[i])
+    return time.perf_counter() - t
+
+
+def cpu_baseline(wl, states, budget_s, workers, cpu):
+    """The CPU oracle, as it stands, on bounded samples of the same workload:
+    one thread on as many instances as fit the budget, then a process pool of
+    `workers` processes over every instance of the batch."""
+    global _POOL_STATES
+    n_el = lambda st: st.rho.size if wl == "pgd_compliance" else st.n
     refs = []
     t0 = time.perf_counter()
-    while done < len(insts) and time.perf_counter() - t0 < budget_s:
-        it = insts[done]
-        if wl == "pgd_compliance":
-            st = it["st"]
-            refs.append(oracle.pgd_step("single", st.rho, st.rho_prev, st.grad, st.grad_prev, st.d_prev,
-                                        st.problem.A, st.g, st.G, st.t, I.LO, I.HI, stream_dtype=np.float32))
-        else:
-            p = it["p"]
-            refs.append(oracle.project(p.kind, p.y, p.A, p.b, p.lo, p.hi, p.C, p.offsets))
-        done += 1
-    el = time.perf_counter() - t0
-    return ({"value": done * n / el, "unit": "elements/s", "cores": 1, "kind": "oracle",
-             "sample": f"{done} full-size instance(s) of the same workload in {el:.1f} s (numpy float64, one thread)"},
-            refs)
+    while len(refs) < len(states) and (not refs or time.perf_counter() - t0 < budget_s):
+        refs.append(_oracle_one(wl, states[len(refs)]))
+    el1 = time.perf_counter() - t0
+    single = {"value": sum(n_el(states[i]) for i in range(len(refs))) / el1, "unit": "elements/s", "cores": 1,
+              "sample": f"{len(refs)} full-size instance(s), one thread, {el1:.1f} s"}
+    out = {"value": single["value"], "unit": "elements/s", "cores": 1, "kind": "oracle",
+           "sample": single["sample"] + " (numpy float64)", "cpu": cpu, "single_thread": single}
+    if workers > 1 and len(states) > 1:
+        import multiprocessing as mp
+        _POOL_STATES = states
+        P = min(workers, len(states))
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(P) as pool:
+            secs = pool.map(_pool_task, [(wl, i) for i in range(len(states))])
+        elp = time.perf_counter() - t0
+        _POOL_STATES = None
+        tot = sum(n_el(st) for st in states)
+        out.update({"value": tot / elp, "cores": P,
+                    "sample": f"all {len(states)} instances of the launch, {P} worker processes "
+                              f"(numpy float64, one thread each), {elp:.1f} s wall, "
+                              f"{sum(secs) / len(secs):.2f} s per instance"})
+        out["pool"] = {"value": tot / elp, "unit": "elements/s", "cores": P, "wall_s": elp}
+    return out, refs
 
 
-def oracle_error(ctx, wl, insts, refs):
+def oracle_error(ctx, wl, states, insts, refs):
     """Error of the GPU result against the float64 oracle on the instances the
-    CPU baseline solved (each solved once more on the GPU from its original
-    inputs, outside the timed region): x relative to |x|, the constraint
-    residual relative to |b_j| (to the row scale sigma_j = sum |a_j| max(|lo|,
-    |hi|) where b_j is zero up to rounding, as in the parity tests), the
-    multiplier relative to itself."""
+    CPU baseline solved on one thread (each solved once more on the GPU from its
+    original inputs, outside the timed region): x relative to |x|, the
+    constraint residual relative to |b_j| (to the row scale sigma_j = sum |a_j|
+    max(|lo|, |hi|) where b_j is zero up to rounding, as in the parity tests),
+    the multiplier relative to itself, free-set disagreements outside the
+    1e-6 band around the bounds, and whether the stated bound covered the
+    multiplier error."""
     import numpy as np
     import torch
     from paper_2511_13905_amd import inputs as I
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
-    xe, re_, le = 0.0, 0.0, 0.0
-    for it, ref in zip(insts, refs):
+    xe, re_, le, mism, covered = 0.0, 0.0, 0.0, 0, True
+    for st, it, ref in zip(states, insts, refs):
+        mask = None
         if wl == "pgd_compliance":
-            st = it["st"]
+            nn = st.rho.size
+            mask = torch.zeros((nn + 31) // 32, dtype=torch.int32, device="cuda:0")
             x, out = ctx.pgd_step("single", it["A"], it["rho"], it["rho_prev"], it["grad"], it["grad_prev"],
                                   dev(st.d_prev), st.g, st.G, st.t, I.LO, I.HI)
             r, o, b = out["proj"], ref["proj"], ref["b"]
             rows = np.atleast_2d(st.problem.A).astype(np.float64)
+            free = None
         else:
-            p = it["p"]
-            x, r = ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C, offsets=p.offsets)
+            p = st
+            mask = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+            x, r = ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=mask)
             o, b = ref, p.b
             rows = p.dense_rows()
+            torch.cuda.synchronize()
+            bits = np.unpackbits(mask.cpu().numpy().view(np.uint8), bitorder="little")[:p.n].astype(bool)
+            free = bits
         sig = np.abs(rows).sum(axis=1) * max(abs(I.LO), abs(I.HI))
         torch.cuda.synchronize()
         xv = x.cpu().numpy().astype(np.float64)
         xe = max(xe, float(np.max(np.abs(xv - o.x) / np.maximum(np.abs(o.x), 1e-300))))
+        z = o.z
+        far = np.minimum(np.abs(z - I.LO), np.abs(z - I.HI)) > 1e-6
+        if free is None:
+            free = (xv != np.float32(I.LO)) & (xv != np.float32(I.HI))
+        mism += int(np.count_nonzero((free != ((z >= I.LO) & (z <= I.HI))) & far))
         for j in range(len(o.resid)):
             bj = abs(float(b[j]))
             scale = bj if bj > 1e-9 * sig[j] else sig[j]
-            re_ = max(re_, abs(r["resid"][j] - o.resid[j]) / max(scale, 1e-300))
+            re_ = max(re_, float(abs(r["resid"][j] - o.resid[j]) / max(scale, 1e-300)))
+            err = abs(r["lam"][j] - o.lam[j])
+            covered = covered and bool(err <= r["lambda_err"][j])
             if o.lam[j] != 0.0:
-                le = max(le, abs(r["lam"][j] - o.lam[j]) / abs(o.lam[j]))
+                le = max(le, float(err / abs(o.lam[j])))
     return {"instances": len(refs), "x_rel_max": xe, "resid_rel_max": re_, "lam_rel_max": le,
-            "tolerance": {"x_rel": 1e-5, "resid_rel": 1e-6}}
+            "free_mismatch_outside_band": mism, "stated_lambda_bound_covers_error": covered,
+            "tolerance": {"x_rel": 1e-5, "resid_rel": 1e-6, "free_band": 1e-6}}
 
 
 if __name__ == "__main__":

@@ -57,8 +57,9 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 5      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
-                                4: pgdto_result.lambda_err, x_err; 5: pgdto_project_noalloc */
+#define PGDTO_VERSION 6      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
+                                4: pgdto_result.lambda_err, x_err; 5: pgdto_project_noalloc;
+                                6: pgdto_project_batch_async, pgdto_pgd_step_batch_async */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
@@ -311,6 +312,27 @@ int pgdto_pgd_step(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_param
                    pgdto_pgd_out* out, void* stream);
 int pgdto_pgd_step_async(pgdto_ctx* ctx, const pgdto_pgd_args* args, const pgdto_params* params,
                          pgdto_pgd_out* out_dev, void* stream);
+
+/* Batching: `count` (1..256) float32 instances solved by ONE persistent
+ * cooperative launch on `stream`, the GPU split into `slots` slots of equal
+ * workgroup ranges (0: min(count, 16)); slot s solves instances s, s + slots,
+ * ... in order, each with the solver of a one-instance launch on its own
+ * workgroups, so every instance's result is bitwise that of pgdto_project
+ * (pgdto_pgd_step) on the same problem.  Results go to results_dev[i]
+ * (device memory, caller-owned, written when the launch completes in stream
+ * order).  Instances must not share output buffers (x, free_mask, dir).
+ * Host arrays are read before the call returns.  The context keeps the
+ * per-slot workspace (grown on the first call that needs more slots: that
+ * call synchronises the device and allocates) and BATCH_RING = 4 pinned
+ * descriptor areas used in turn (a call waits for the launch four calls back
+ * before it rewrites that area).  Not for HIP graph capture: the kernel reads
+ * descriptors the host writes per call.  PGDTO_ERR_ARG for a float64
+ * instance, count out of range or any invalid instance (nothing launched). */
+int pgdto_project_batch_async(pgdto_ctx* ctx, const pgdto_problem* probs, int count, const pgdto_params* params,
+                              pgdto_result* results_dev, int slots, void* stream);
+/* The same for Algorithm 3 steps (pgdto_pgd_step_async per instance). */
+int pgdto_pgd_step_batch_async(pgdto_ctx* ctx, const pgdto_pgd_args* args, int count, const pgdto_params* params,
+                               pgdto_pgd_out* outs_dev, int slots, void* stream);
 
 /* Serving: continuous batching of projection and Algorithm 3 requests.
  *

@@ -20,6 +20,7 @@ OK, PENDING, QUEUED = 0, 1, 2
 ERR_ARG, ERR_HIP, ERR_NOMEM, ERR_UNKNOWN_TICKET, ERR_TIMEOUT, ERR_BUSY, ERR_CANCELLED, ERR_SCRATCH = (
     -1, -2, -3, -4, -5, -6, -7, -8)
 NOALLOC_SCRATCH_BYTES = 1466752
+BATCH_MAX = 256
 CONVERGED, INACTIVE, INFEASIBLE, MAXITER, NONFINITE = 0, 1, 2, 3, 4
 OUTCOME_NAMES = {0: "converged", 1: "inactive", 2: "infeasible", 3: "maxiter", 4: "nonfinite"}
 F32, F64 = 0, 1
@@ -109,6 +110,9 @@ SIGNATURES = {
     "pgdto_project_noalloc": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, _VP]),
     "pgdto_pgd_step": (C.c_int, [_VP, C.POINTER(PgdArgs), C.POINTER(Params), C.POINTER(PgdOut), _VP]),
     "pgdto_pgd_step_async": (C.c_int, [_VP, C.POINTER(PgdArgs), C.POINTER(Params), _VP, _VP]),
+    "pgdto_project_batch_async": (C.c_int, [_VP, C.POINTER(Problem), C.c_int, C.POINTER(Params), _VP, C.c_int, _VP]),
+    "pgdto_pgd_step_batch_async": (C.c_int, [_VP, C.POINTER(PgdArgs), C.c_int, C.POINTER(Params), _VP, C.c_int,
+                                             _VP]),
     "pgdto_batch_create": (C.c_int, [_VP, C.POINTER(BatchCfg), C.POINTER(_VP)]),
     "pgdto_batch_submit": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_uint64)]),
     "pgdto_batch_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(Result)]),

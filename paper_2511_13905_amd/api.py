@@ -6,12 +6,34 @@ projection runs in the HIP kernels of libpgdto.so.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
+import weakref
 
 import torch
 
 from . import _native as N
+
+# Open handles, closed in a fixed order when the interpreter exits (batches,
+# whose executor threads and launches use a context's device, before
+# contexts), before Python tears down modules and the HIP runtime its own
+# exit handlers: no library call is left to a finalizer at shutdown.
+_LIVE_BATCHES = weakref.WeakSet()
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+def close_all():
+    """Close every open Batch, then every open Context, then wait for the device."""
+    for b in list(_LIVE_BATCHES):
+        b.close()
+    for c in list(_LIVE_CONTEXTS):
+        c.close()
+    if torch.cuda.is_initialized():
+        torch.cuda.synchronize()
+
+
+atexit.register(close_all)
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -48,8 +70,8 @@ def aligned_rows(A: torch.Tensor) -> torch.Tensor:
     m, n = A.shape
     esz = A.element_size()
     vec = 16 // esz
-    if A.stride(1) == 1 and (A.stride(0) * esz) % 16 == 0 and A.data_ptr() % 16 == 0 and A.stride(0) >= n:
-        return A
+    if A.stride(1) == 1 and A.data_ptr() % 16 == 0 and (m == 1 or ((A.stride(0) * esz) % 16 == 0 and A.stride(0) >= n)):
+        return A                         # one row: its stride is never used
     lda = (n + vec - 1) // vec * vec
     buf = torch.zeros((m, lda), dtype=A.dtype, device=A.device)
     buf[:, :n].copy_(A)
@@ -145,6 +167,7 @@ class Context:
         h = C.c_void_p()
         _check(N.lib().pgdto_ctx_create(device, C.byref(h)), "pgdto_ctx_create")
         self.h = h
+        _LIVE_CONTEXTS.add(self)
 
     def autotune(self, enable=1) -> int:
         """pgdto_ctx_autotune: grid autotuning per shape class (returns the previous setting)."""
@@ -160,6 +183,7 @@ class Context:
         if getattr(self, "h", None):
             N.lib().pgdto_ctx_destroy(self.h)
             self.h = None
+            _LIVE_CONTEXTS.discard(self)
 
     def __del__(self):
         try:
@@ -227,6 +251,45 @@ class Context:
         st = N.lib().pgdto_pgd_step(self.h, C_byref(a), C_byref(p), C_byref(out), _stream(self.device, stream))
         _check(st, "pgdto_pgd_step")
         return x, out.to_dict()
+
+    # ------------------------------------------------------------ one-launch batches
+    def project_batch_async(self, problems, results_buf: torch.Tensor, params=None, slots: int = 0, stream=None):
+        """pgdto_project_batch_async: problems is a list of (kind, y, A, b, lo, hi,
+        C, offsets, x) tuples (float32, A rows 16-byte aligned, distinct x);
+        the result structs land in results_buf (uint8 device tensor of at
+        least len(problems) * result_nbytes() bytes)."""
+        if results_buf.numel() * results_buf.element_size() < len(problems) * result_nbytes():
+            raise ValueError("results_buf holds fewer result structs than problems")
+        keep = _Keep()
+        arr = (N.Problem * len(problems))()
+        for i, (kind, y, A, b, lo, hi, C_pen, offsets, x) in enumerate(problems):
+            arr[i], _, _ = problem_struct(kind, y, A, b, lo, hi, C_pen, offsets, x, None, keep, copy_ok=False)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        st = N.lib().pgdto_project_batch_async(self.h, arr, len(problems), C_byref(p), results_buf.data_ptr(),
+                                               int(slots), _stream(self.device, stream))
+        _check(st, "pgdto_project_batch_async")
+
+    def pgd_step_batch_async(self, steps, outs_buf: torch.Tensor, params=None, slots: int = 0, stream=None):
+        """pgdto_pgd_step_batch_async: steps is a list of dicts with the
+        arguments of pgd_step (kind, A, rho, rho_prev, grad, grad_prev, d, g, G,
+        t, lo, hi, and optionally C, offsets, x and hyper-parameters); x must be
+        given.  The pgdto_pgd_out structs land in outs_buf."""
+        if outs_buf.numel() * outs_buf.element_size() < len(steps) * result_nbytes(pgd=True):
+            raise ValueError("outs_buf holds fewer output structs than steps")
+        keep = _Keep()
+        arr = (N.PgdArgs * len(steps))()
+        for i, s in enumerate(steps):
+            s = dict(s)
+            hyper = {k: s.pop(k) for k in list(s) if k in ("cg_rule", "t_warmup", "alpha_max", "alpha_fallback",
+                                                          "omega", "eps_alpha", "tol_viol", "tol")}
+            arr[i], _ = self._pgd_struct(s["kind"], s["A"], s["rho"], s.get("rho_prev"), s["grad"],
+                                         s.get("grad_prev"), s["d"], s["g"], s["G"], s["t"], s["lo"], s["hi"],
+                                         s.get("C", math.inf), s.get("offsets"), s["x"], hyper, keep,
+                                         copy_ok=False)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        st = N.lib().pgdto_pgd_step_batch_async(self.h, arr, len(steps), C_byref(p), outs_buf.data_ptr(), int(slots),
+                                                _stream(self.device, stream))
+        _check(st, "pgdto_pgd_step_batch_async")
 
     def pgd_step_async(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, out_buf,
                        C=math.inf, offsets=None, x=None, params=None, stream=None, lam0=None, **hyper):
@@ -297,6 +360,7 @@ class Batch:
         self.h = h
         self.ctx = ctx
         self._live = {}
+        _LIVE_BATCHES.add(self)
 
     def shape(self):
         s, w = C.c_int32(), C.c_int32()
@@ -364,6 +428,7 @@ class Batch:
             N.lib().pgdto_batch_destroy(self.h)
             self.h = None
             self._live.clear()
+            _LIVE_BATCHES.discard(self)
 
     def __del__(self):
         try:

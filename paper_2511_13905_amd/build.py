@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpgdto.so")
 ORACLE_C = os.path.join(ROOT, "oracle")
 
-SOURCES = ["pgdto_kernels.hip", "pgdto_host.cpp", "pgdto_serve.cpp", "pgdto_server.cpp"]
+SOURCES = ["pgdto_kernels.hip", "pgdto_host.cpp", "pgdto_serve.cpp", "pgdto_server.cpp", "pgdto_many.cpp"]
 
 # Packed-FP32 instructions are disabled: hipcc -O3 forms them from float2
 # code and some forms have given wrong results on these machines.

@@ -23,6 +23,16 @@ struct pgdto_ctx {
   std::unordered_map<uint64_t, int> tuned_grid;
   int forced_grid = 0;                        // set while a candidate is timed
   uint64_t door_wait = pgdto::DOOR_WAIT_DEFAULT;   // arrival-door wait of one-instance launches (100 MHz ticks)
+  // one-launch batches: per-slot workspace (grown on demand) and pinned
+  // descriptor areas used in turn, each with the event of its last launch
+  int bt_cap = 0;                             // co-resident workgroups of the batch kernel
+  int bt_slots = 0;                           // slots the workspace holds
+  double* bt_part = nullptr;
+  uint64_t* bt_sync = nullptr;
+  pgdto::Desc* bt_jobs[pgdto::BATCH_RING] = {};
+  hipEvent_t bt_ev[pgdto::BATCH_RING] = {};
+  int bt_next = 0;
+  uint64_t bt_seq = 0;
 };
 
 namespace pgdto {

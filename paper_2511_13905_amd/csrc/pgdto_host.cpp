@@ -157,6 +157,12 @@ extern "C" int pgdto_ctx_destroy(pgdto_ctx* c) {
   if (c->res_dev) (void)hipFree(c->res_dev);
   if (c->res_host) (void)hipHostFree(c->res_host);
   if (c->trace) (void)hipFree(c->trace);
+  if (c->bt_part) (void)hipFree(c->bt_part);
+  if (c->bt_sync) (void)hipFree(c->bt_sync);
+  for (int r = 0; r < BATCH_RING; ++r) {
+    if (c->bt_jobs[r]) (void)hipHostFree(c->bt_jobs[r]);
+    if (c->bt_ev[r]) (void)hipEventDestroy(c->bt_ev[r]);
+  }
   delete c;
   return PGDTO_OK;
 }

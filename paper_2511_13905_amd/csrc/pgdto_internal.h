@@ -122,9 +122,27 @@ struct SrvArgs {
 
 constexpr uint64_t SRV_LEAVE = ~0ull;
 
+// One launch over a fixed list of instances (pgdto_project_batch_async,
+// pgdto_pgd_step_batch_async): slot s solves instances s, s + slots, ... in
+// order, on its own workgroups, partial sums and barrier words.
+struct BatchArgs {
+  const Desc* jobs;            // pinned [count], written by the host before the launch
+  void* results;               // device: pgdto_result[count] or pgdto_pgd_out[count]
+  double* part;                // device: per-slot partial sums, stride part_stride
+  uint64_t* sync;              // device: per-slot barrier words, stride sync_stride
+  uint64_t part_stride, sync_stride;
+  uint64_t epoch_base;         // launch-unique: the k-th job of a slot uses epoch_base + (k << 16)
+  int32_t count, slots, wg_per_slot, is_pgd;
+};
+constexpr int BATCH_MAX = 256;          // instances per batch launch
+constexpr int BATCH_RING = 4;           // pinned descriptor areas per context (reused in turn)
+constexpr int BATCH_JOB_SHIFT = 16;     // passes per job stay below 2^16
+
 hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative);
 int max_coresident(int kind, int dtype, int m, int device);
 hipError_t launch_mark_error(void* result, int is_pgd, hipStream_t stream);
 hipError_t launch_server(const SrvArgs& a, hipStream_t stream);
 int server_coresident(int device);     // workgroups of the server kernel that fit at once
+hipError_t launch_batch(const BatchArgs& a, hipStream_t stream);
+int batch_coresident(int device);      // workgroups of the batch kernel that fit at once
 }  // namespace pgdto

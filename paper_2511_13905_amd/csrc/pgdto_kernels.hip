@@ -163,6 +163,27 @@ __device__ __forceinline__ double recip(double av) {
 }
 __device__ __forceinline__ double breakpoint(double y, double av, double bound) { return (y - bound) * recip(av); }
 
+// ------------------------------------------------------------------ cross-workgroup publication
+// Values one workgroup writes for another (per-tile partial sums, the pass
+// totals) are stored with agent-coherent stores, which write through this
+// XCD's L2 to memory, and read with agent-coherent loads, which do not hit a
+// stale line in the reader's L2.  Every wave that stores such values waits
+// for its own stores to complete before the workgroup barrier that precedes
+// the flag or go word: a barrier orders the waves of one workgroup only, and
+// a release by another wave covers that wave's own stores, so without the
+// wait a store of wave k could still be in flight when the flag is seen.
+// With the data in memory before the flag is raised, flags and go words need
+// no release fence (no write-back of the whole L2 per workgroup and pass).
+__device__ __forceinline__ void publish(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double fetch_published(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima): this wave's
+// vector memory operations, stores included, have completed.
+__device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ------------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -202,8 +223,9 @@ __device__ __forceinline__ void block_to_part(const double (&acc)[NV], int nv, u
         r = mx ? fmax(r, q) : r + q;
       }
       r = mx ? wave_max(r) : wave_sum(r);
-      if (lane == 0) pb[v * TILES_PAD + tile] = r;
+      if (lane == 0) publish(&pb[v * TILES_PAD + tile], r);
     }
+    if (c + NWAVE >= NV) wait_own_stores();   // before the last barrier
     __syncthreads();
   }
 }
@@ -232,7 +254,7 @@ __device__ __forceinline__ void reduce_tiles(const double* pb, int nv, uint64_t 
 #pragma unroll
         for (int k = 0; k < LMAX; ++k) {
           const int t = t0 + k * P;
-          q[k] = (t < te) ? pb[v * TILES_PAD + t] : (mx ? -INFINITY : 0.0);
+          q[k] = (t < te) ? fetch_published(&pb[v * TILES_PAD + t]) : (mx ? -INFINITY : 0.0);
         }
 #pragma unroll
         for (int k = 0; k < LMAX; ++k) r = mx ? fmax(r, q[k]) : r + q[k];
@@ -325,7 +347,8 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
   __syncthreads();
   if (threadIdx.x == 0) {
     *abort_flag = 0;
-    __hip_atomic_store(&W.flags[(size_t)wid * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // the partials of every wave are in memory (block_to_part waited for them)
+    __hip_atomic_store(&W.flags[(size_t)wid * FLAG_STRIDE], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (wid == 0) {
@@ -339,10 +362,9 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
     }
     if (!ok) atomicOr(abort_flag, 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (*abort_flag) __hip_atomic_store(W.err, d.epoch0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    // the partials are read with agent-coherent loads (no acquire fence, which
+    // would invalidate this XCD's whole L2)
+    if (threadIdx.x == 0 && *abort_flag) __hip_atomic_store(W.err, d.epoch0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (*abort_flag) return false;
     trace_put(d, pass_no, 2, clk());
@@ -351,16 +373,17 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
     if (in_rep) {
       for (int i = threadIdx.x; i < NREP * ntot; i += BLOCK) {
         const int r = i / ntot, k = i - r * ntot;
-        ((double*)(W.rep + (size_t)r * REP_WORDS + 1))[k] = tot[k];
+        publish((double*)(W.rep + (size_t)r * REP_WORDS + 1) + k, tot[k]);
       }
     } else {
-      for (int i = threadIdx.x; i < ntot; i += BLOCK) W.totals[i] = tot[i];
+      for (int i = threadIdx.x; i < ntot; i += BLOCK) publish(W.totals + i, tot[i]);
     }
+    wait_own_stores();
     __syncthreads();
-    // one wave raises every copy of the go word (one release for all of them)
+    // one wave raises every copy of the go word; the totals of every wave are in memory
     if (threadIdx.x < 64) {
       for (int r = threadIdx.x; r < NREP; r += 64)
-        __hip_atomic_store(W.rep + (size_t)r * REP_WORDS, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(W.rep + (size_t)r * REP_WORDS, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return true;
   }
@@ -426,6 +449,7 @@ struct TileGeom {
   int64_t ts, te;         // tile element range (ts 32-aligned)
   int64_t p0;             // first vector slot of the tile
   int nsweep;             // vector slots per thread (uniform over the block)
+  bool interior;          // a whole tile inside its segment: every slot full, nsweep even
 };
 
 template <typename T>
@@ -445,6 +469,9 @@ __device__ __forceinline__ TileGeom tile_geom(const Desc& d, int tile) {
   g.p0 = ts / V;
   const int64_t nslots = (te - ts + V - 1) / V;
   g.nsweep = (int)((nslots + BLOCK - 1) / BLOCK);
+  // tile_elems is a multiple of 2 * BLOCK * V, so a whole tile has an even
+  // number of full slots per thread
+  g.interior = ts >= g.sstart && ts + d.tile_elems <= g.send;
   return g;
 }
 
@@ -471,6 +498,33 @@ __device__ __forceinline__ bool slot(const TileGeom& g, int k, int64_t& e0, bool
 template <typename T, int NS, int U, class F>
 __device__ __forceinline__ void stream_tile(const TileGeom& g, int64_t n, const T* const* ptrs, F&& f) {
   constexpr int V = VT<T>::N;
+  static_assert(U == 1 || U == 2 || U == 4, "chunk of 1, 2 or 4 slots");
+  if (g.interior) {
+    // every slot whole and inside the segment: no per-element masks or
+    // address clamps (f sees a constant full mask and folds its checks away)
+    constexpr uint32_t FULL = (1u << V) - 1u;
+    const int64_t base = (g.p0 + (int64_t)threadIdx.x) * V;
+    auto chunk = [&](int k0, auto uc) __attribute__((always_inline)) {
+      constexpr int UU = decltype(uc)::value;
+      T buf[UU][NS][V];
+      int64_t e0[UU];
+#pragma unroll
+      for (int u = 0; u < UU; ++u) e0[u] = base + (int64_t)(k0 + u) * (BLOCK * V);
+#pragma unroll
+      for (int u = 0; u < UU; ++u)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) ld_vec_whole<T>(gptr(ptrs[q]), e0[u], buf[u][q]);
+#pragma unroll
+      for (int u = 0; u < UU; ++u) f(buf[u], e0[u], FULL, true);
+    };
+    // nsweep is even here: chunks of U, then at most one chunk of 2
+    int k0 = 0;
+    for (; k0 + U <= g.nsweep; k0 += U) chunk(k0, std::integral_constant<int, U>{});
+    if constexpr (U == 4) {
+      if (k0 < g.nsweep) chunk(k0, std::integral_constant<int, 2>{});
+    }
+    return;
+  }
   for (int k0 = 0; k0 < g.nsweep; k0 += U) {
     T buf[U][NS][V];
     int64_t e0[U];
@@ -1338,7 +1392,11 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 }
 
 // Zero the free-mask words of this workgroup's tiles (before the first grid
-// barrier; the final pass sets bits only where elements are free).
+// barrier; the final pass sets bits only where elements are free).  A word at
+// a block boundary belongs to two tiles, whose workgroups may sit on
+// different XCDs and both set bits in it with device atomics: the zeros are
+// written through to memory and complete before the first barrier, so that
+// no dirty zero is left in an L2 to be written back over those bits.
 template <typename T>
 __device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
   if (!d.free_mask) return;
@@ -1346,8 +1404,10 @@ __device__ __forceinline__ void clear_mask_tiles(const Desc& d) {
   for (int tile = wid; tile < d.ntiles; tile += G) {
     const TileGeom g = tile_geom<T>(d, tile);
     const int64_t w0 = g.ts >> 5, w1 = (g.te + 31) >> 5;
-    for (int64_t w = w0 + threadIdx.x; w < w1; w += BLOCK) d.free_mask[w] = 0u;
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += BLOCK)
+      __hip_atomic_store(&d.free_mask[w], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  wait_own_stores();
 }
 
 // ------------------------------------------------------------------ arrival door
@@ -2419,6 +2479,71 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
   }
 }
 
+// ================================================================== batch kernel
+// Many instances in one launch: slot s owns workgroups [s * W, (s + 1) * W)
+// and solves instances s, s + slots, s + 2 slots, ... of the list in order,
+// with the same solver and the same per-slot workspace as the server.  The
+// k-th instance of a slot takes barrier epochs from epoch_base + (k << 16),
+// above every flag its predecessors left.  A workgroup that finishes an
+// instance early starts the next one at once: the next instance's first
+// totals need this workgroup's flag, so no workgroup of the slot can still
+// be reading the previous instance's totals when they are overwritten.
+// float32 streams only.
+__global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
+  __shared__ BatchArgs a;
+  Desc& sd = srv_sd;
+  {
+    const uint32_t* src = (const uint32_t*)__builtin_amdgcn_kernarg_segment_ptr();
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
+    for (int i = threadIdx.x; i < (int)(sizeof(BatchArgs) / 4); i += BLOCK) dst[i] = src[i];
+    __syncthreads();
+  }
+  const int W = a.wg_per_slot;
+  const int slot = (int)blockIdx.x / W;
+  if (slot >= a.slots) return;
+  for (int k = 0;; ++k) {
+    const int64_t i = (int64_t)slot + (int64_t)k * a.slots;
+    if (i >= a.count) return;
+    {
+      // the instance's descriptor (pinned host memory, written before the launch)
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.jobs + i);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&sd);
+      for (int w = threadIdx.x; w < (int)(sizeof(Desc) / 4); w += BLOCK)
+        dst[w] = __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        sd.wg_base = slot * W;
+        sd.wg_count = W;
+        sd.part = a.part + (size_t)slot * a.part_stride;
+        sd.sync = a.sync + (size_t)slot * a.sync_stride;
+        sd.epoch0 = a.epoch_base + ((uint64_t)k << BATCH_JOB_SHIFT);
+        sd.pgd = a.is_pgd;
+        sd.result = a.is_pgd ? (void*)((pgdto_pgd_out*)a.results + i) : (void*)((pgdto_result*)a.results + i);
+        sd.trace = nullptr;
+      }
+      __syncthreads();
+    }
+    clear_mask_tiles<float>(sd);
+    if (sd.kind == PGDTO_COUPLED) {
+      switch (sd.m) {
+        case 1: srv_solve_coupled<1>(); break;
+        case 2: srv_solve_coupled<2>(); break;
+        case 3: srv_solve_coupled<3>(); break;
+        case 4: srv_solve_coupled<4>(); break;
+        case 5: srv_solve_coupled<5>(); break;
+        case 6: srv_solve_coupled<6>(); break;
+        case 7: srv_solve_coupled<7>(); break;
+        default: srv_solve_coupled<8>(); break;
+      }
+    } else if (srv_sd.eq_mask) {
+      srv_solve_1d<true>();
+    } else {
+      srv_solve_1d<false>();
+    }
+    __syncthreads();
+  }
+}
+
 // Marks a result as failed (used by the host after a failed launch).
 __global__ void k_mark_error(void* result, int is_pgd) {
   if (threadIdx.x == 0 && result) {
@@ -2474,6 +2599,19 @@ hipError_t launch_server(const SrvArgs& a, hipStream_t stream) {
 int server_coresident(int device) {
   int nb = 0, ncu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_server, BLOCK, 0) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return nb * ncu;
+}
+
+hipError_t launch_batch(const BatchArgs& a, hipStream_t stream) {
+  BatchArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel((const void*)k_batch, dim3(a.slots * a.wg_per_slot), dim3(BLOCK), args, 0, stream);
+}
+
+int batch_coresident(int device) {
+  int nb = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_batch, BLOCK, 0) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   return nb * ncu;
 }
