@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-pool", type=int, default=128,
                     help="distinct request instances the served stream cycles through")
+    ap.add_argument("--compact", action="store_true", help="turn the free-set compaction on")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes that generate the inputs (1 under a profiler)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -131,17 +132,32 @@ def host_cpu():
 
 
 # ---------------------------------------------------------------- byte model
-def pgd_bytes(n, passes):
+def compact_split(r):
+    """(search passes over every element, kept pairs, passes over the kept
+    pairs only) of one result: the free-set compaction pass reads every
+    element and writes the kept (y, a) pairs; later search passes read only
+    those pairs."""
+    kept = max(0, r.get("n_compact", -1))
+    pc = r.get("passes_compacted", 0) if r.get("n_compact", -1) >= 0 else 0
+    return r["iters_search"] - pc, kept, pc
+
+
+def pgd_bytes(n, r):
     """Algorithmic bytes of one pgd_step (float32 streams): pass R reads
     rho, rho_prev, grad, grad_prev, a; the zero pass reads rho, grad, d, a and
-    writes d, rho~; each search pass reads rho~, a; the final pass reads rho~,
-    a, rho and writes x."""
-    return n * ESZ * (5 + 6 + 2 * (passes - 3) + 4)
+    writes d, rho~; each full search pass reads rho~, a (the compaction pass
+    also writes the kept pairs, each later pass reads them); the final pass
+    reads rho~, a, rho and writes x."""
+    full, kept, pc = compact_split(r)
+    return n * ESZ * (5 + 6 + 2 * full + 4) + kept * 2 * ESZ * (1 + pc)
 
 
-def proj_bytes(n, rows, passes):
-    """Every pass reads y and the rows; the final pass also writes x."""
-    return passes * n * ESZ * (1 + rows) + n * ESZ
+def proj_bytes(n, rows, r):
+    """Every full pass reads y and the rows (kept pairs as above for the
+    1-D searches); the final pass also writes x."""
+    full, kept, pc = compact_split(r)
+    other = r["passes"] - r["iters_search"]          # zero pass, Stage 1, Newton, final ...
+    return (other + full) * n * ESZ * (1 + rows) + n * ESZ + kept * 2 * ESZ * (1 + pc)
 
 
 def main():
@@ -189,6 +205,7 @@ def main():
                  for st in states]
         for it in insts:
             it["x"] = torch.empty_like(it["rho"])
+            it["work"] = torch.empty_like(it["rho"])     # free-set compaction scratch
         n, m, rows = insts[0]["rho"].numel(), 1, 1
         workload = (f"pgd_step on {B} distinct instances per launch, single linearized compliance row, "
                     "256x128x128 grid (n=4194304 each), float32 streams")
@@ -211,12 +228,14 @@ def main():
     res_buf = torch.zeros(nres * B, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
+    params = {"compact": 1 if args.compact else 0}
+
     def launch(slots):
         if is_pgd:
-            ctx.pgd_step_batch_async(insts, res_buf, slots=slots)
+            ctx.pgd_step_batch_async(insts, res_buf, slots=slots, params=params)
         else:
             ctx.project_batch_async([(it["p"].kind, it["y"], it["A"], it["p"].b, it["p"].lo, it["p"].hi, it["p"].C,
-                                      it["p"].offsets, it["x"]) for it in insts], res_buf, slots=slots)
+                                      it["p"].offsets, it["x"]) for it in insts], res_buf, slots=slots, params=params)
 
     def timed(slots, k):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -266,10 +285,10 @@ def main():
     passes = [r["passes"] for r in proj]
     errors = [r["error"] for r in proj]
     if is_pgd:
-        bytes_launch = sum(pgd_bytes(n, p) for p in passes)
+        bytes_launch = sum(pgd_bytes(n, r) for r in proj)
         compulsory = B * n * ESZ * (6 + 2)
     else:
-        bytes_launch = sum(proj_bytes(st.n, rows, p) for st, p in zip(states, passes))
+        bytes_launch = sum(proj_bytes(st.n, rows, r) for st, r in zip(states, proj))
         compulsory = sum(st.n * ESZ * (rows + 2) for st in states)
     elems = B * n if is_pgd else sum(st.n for st in states)
     achieved = bytes_launch / (kern_ms * 1e-3)
@@ -290,6 +309,9 @@ def main():
         "config": {"workload": workload, "instances_per_launch": B, "elements_per_launch": elems,
                    "slots": slots, "slot_sweep_ms": sweep, "grid_workgroups": grid, "tiles_per_instance": tiles,
                    "passes_per_instance": {"mean": sum(passes) / B, "min": min(passes), "max": max(passes)},
+                   "compaction": {"on": bool(args.compact),
+                                  "kept_fraction_mean": sum(max(0, r["n_compact"]) for r in proj) / B / n,
+                                  "passes_on_kept_mean": sum(r["passes_compacted"] for r in proj) / B},
                    "latency_ms": {"p50": per[len(per) // 2],
                                   "p99": per[min(len(per) - 1, int(math.ceil(0.99 * len(per))) - 1)]},
                    "wall_s": wall, "device_errors": sorted(set(errors)), "kernel_sha": kernel_sha(),
@@ -338,11 +360,12 @@ def single_bench(ctx, insts, is_pgd, n, rows, args):
         it = insts[i % R]
         if is_pgd:
             ctx.pgd_step_async("single", it["A"], it["rho"], it["rho_prev"], it["grad"], it["grad_prev"], it["d"],
-                               it["g"], it["G"], it["t"], I.LO, I.HI, bufs[i % R], x=it["x"])
+                               it["g"], it["G"], it["t"], I.LO, I.HI, bufs[i % R], x=it["x"], work=it["work"],
+                               params={"compact": 1 if args.compact else 0})
         else:
             p = it["p"]
             ctx.project_async(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, bufs[i % R], C=p.C, offsets=p.offsets,
-                              x=it["x"])
+                              x=it["x"], params={"compact": 1 if args.compact else 0})
 
     for i in range(4):
         launch(i)
@@ -373,7 +396,8 @@ def single_bench(ctx, insts, is_pgd, n, rows, args):
     del flush_src, flush_dst
     mean_ms = sum(warm) / len(warm)
     mean_passes = sum(passes) / len(passes)
-    alg = pgd_bytes(n, mean_passes) if is_pgd else proj_bytes(n, rows, mean_passes)
+    pr = [(r["proj"] if is_pgd else r) for r in res]
+    alg = sum(pgd_bytes(n, r) if is_pgd else proj_bytes(n, rows, r) for r in pr) / len(pr)
     return {"launch": "pgdto_pgd_step_async" if is_pgd else "pgdto_project_async",
             "instances_rotated": R, "passes_mean": mean_passes, "grid_tiles": list(ctx.last_launch()),
             "warm_ms": {"mean": mean_ms, "p50": warm[len(warm) // 2], "p99": warm[-1]},
@@ -520,7 +544,7 @@ def server_batch_bench(ctx, insts, args):
         ns.append(p.n)
         if i < len(insts):
             _, r = ctx.project(p.kind, it["y"], it["A"], p.b, p.lo, p.hi, p.C)
-            passes[i] = r["passes"]
+            passes[i] = r
         per.append(proj_bytes(p.n, 1, passes[i % len(insts)]))
     torch.cuda.synchronize()
     alg = sum(per)

@@ -57,9 +57,10 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 6      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
+#define PGDTO_VERSION 7      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
                                 4: pgdto_result.lambda_err, x_err; 5: pgdto_project_noalloc;
-                                6: pgdto_project_batch_async, pgdto_pgd_step_batch_async */
+                                6: pgdto_project_batch_async, pgdto_pgd_step_batch_async;
+                                7: pgdto_params.compact, pgdto_pgd_args.work, autotune save/load */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
@@ -162,6 +163,22 @@ typedef struct {
   int32_t ncp;           /* pgdto_ncp                                        */
   int32_t stage1;        /* COUPLED: 1 = run Stage 1 (default), 0 = skip      */
   double c1, c2;         /* Armijo / curvature constants (1e-4, 0.9)         */
+  int32_t compact;       /* 1-D searches: 1 = free-set compaction
+                            (Sec. 4.2.1, the remark that saturated variables
+                            add nothing to the Jacobian): once a row's bracket
+                            lies within 25% of its upper end, each whole tile
+                            folds the elements whose state (below / inside /
+                            above the box) is the same at both bracket ends
+                            into three sums and later passes stream only the
+                            other elements' (y, a) pairs, kept in scratch:
+                            x for a projection, pgdto_pgd_args.work for an
+                            Algorithm 3 step (no compaction without it);
+                            0 (default) = every pass streams every element.
+                            Results agree to rounding; every route
+                            (one-instance, batch, served) gives the same
+                            bits for one setting.  A separate kernel
+                            instantiation, so the default keeps its
+                            registers                                        */
 } pgdto_params;
 
 typedef struct {
@@ -201,6 +218,12 @@ typedef struct {
    * dtype at max(|lo|, |hi|): a bound on max_i |x_i - x*_i|. */
   double lambda_err[PGDTO_MAX_BLOCKS];
   double x_err;
+  int64_t n_compact;     /* 1-D searches: elements the free-set compaction kept
+                            for the later passes (summed over rows / blocks;
+                            see pgdto_params.compact); -1 when none ran      */
+  int32_t passes_compacted;  /* search passes that streamed only the kept
+                            elements (max over rows / blocks)                */
+  int32_t reserved;
 } pgdto_result;
 
 typedef struct {
@@ -222,6 +245,12 @@ typedef struct {
   double eps_alpha;      /* 1e-6                                              */
   double tol_viol;       /* tol_N of the fallback rule (1e-6)                 */
   double tol;            /* stop test ||rho_{t+1}-rho_t|| / ||rho_{t+1}||     */
+  void* work;            /* optional device [n] of the stream dtype: scratch
+                            for the free-set compaction (see pgdto_params.
+                            compact); NULL: none.  May be the caller's
+                            rho_prev or grad_prev buffer (they are read only
+                            in the first pass); must not overlap x, dir, rho
+                            or grad                                          */
 } pgdto_pgd_args;
 
 typedef struct {
@@ -253,6 +282,15 @@ int pgdto_ctx_destroy(pgdto_ctx* ctx);
  * forget.  Results do not depend on the choice (bitwise).  Returns the
  * previous setting or PGDTO_ERR_ARG. */
 int pgdto_ctx_autotune(pgdto_ctx* ctx, int enable);
+/* Persist the autotuner's choices across processes: save writes every shape
+ * class tuned on this context to the text file `path` (a header with the
+ * library version and the device's architecture and compute-unit count,
+ * then one "class grid" line each) and returns how many; load adds the
+ * choices of such a file to the context and returns how many (0 when the
+ * file was written for another device or library version).  PGDTO_ERR_ARG
+ * for a file that cannot be opened. */
+int pgdto_ctx_autotune_save(pgdto_ctx* ctx, const char* path);
+int pgdto_ctx_autotune_load(pgdto_ctx* ctx, const char* path);
 /* Two more environment variables read at context creation, for studies of
  * the launch (results do not depend on either, bitwise):
  *   PGDTO_GRID=k       one-instance launches use at most k workgroups (the

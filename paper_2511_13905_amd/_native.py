@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpgdto.so")
+# PGDTO_LIB selects another build of the same library (the sanitizer build,
+# libpgdto_san.so, for the CPU test suite)
+LIB_PATH = os.environ.get("PGDTO_LIB") or os.path.join(HERE, "libpgdto.so")
 
 MAX_M = 8
 MAX_BLOCKS = 64
@@ -45,7 +47,7 @@ class Params(C.Structure):
     _fields_ = [("tol_b", C.c_double), ("tol_n", C.c_double),
                 ("max_search", C.c_int32), ("max_newton", C.c_int32), ("max_ls", C.c_int32),
                 ("search", C.c_int32), ("ncp", C.c_int32), ("stage1", C.c_int32),
-                ("c1", C.c_double), ("c2", C.c_double)]
+                ("c1", C.c_double), ("c2", C.c_double), ("compact", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -55,7 +57,8 @@ class Result(C.Structure):
                 ("lambda_", C.c_double * MAX_BLOCKS), ("resid", C.c_double * MAX_BLOCKS),
                 ("slack", C.c_double * MAX_BLOCKS), ("row_outcome", C.c_int32 * MAX_BLOCKS),
                 ("res_inf", C.c_double), ("lambda_width", C.c_double), ("kappa", C.c_double),
-                ("lambda_err", C.c_double * MAX_BLOCKS), ("x_err", C.c_double)]
+                ("lambda_err", C.c_double * MAX_BLOCKS), ("x_err", C.c_double), ("n_compact", C.c_int64),
+                ("passes_compacted", C.c_int32), ("reserved", C.c_int32)]
 
     def to_dict(self) -> dict:
         m = self.m
@@ -67,7 +70,8 @@ class Result(C.Structure):
                 "slack": list(self.slack[:m]),
                 "row_outcome": [OUTCOME_NAMES.get(o, str(o)) for o in self.row_outcome[:m]],
                 "res_inf": self.res_inf, "lambda_width": self.lambda_width, "kappa": self.kappa,
-                "lambda_err": list(self.lambda_err[:m]), "x_err": self.x_err}
+                "lambda_err": list(self.lambda_err[:m]), "x_err": self.x_err, "n_compact": self.n_compact,
+                "passes_compacted": self.passes_compacted}
 
 
 class PgdArgs(C.Structure):
@@ -76,7 +80,8 @@ class PgdArgs(C.Structure):
                 ("g", C.POINTER(C.c_double)), ("G", C.POINTER(C.c_double)), ("t", C.c_int64),
                 ("t_warmup", C.c_int32), ("cg_rule", C.c_int32),
                 ("alpha_max", C.c_double), ("alpha_fallback", C.c_double), ("omega", C.c_double),
-                ("eps_alpha", C.c_double), ("tol_viol", C.c_double), ("tol", C.c_double)]
+                ("eps_alpha", C.c_double), ("tol_viol", C.c_double), ("tol", C.c_double),
+                ("work", C.c_void_p)]
 
 
 class PgdOut(C.Structure):
@@ -105,6 +110,8 @@ SIGNATURES = {
     "pgdto_ctx_destroy": (C.c_int, [_VP]),
     "pgdto_ctx_autotune": (C.c_int, [_VP, C.c_int]),
     "pgdto_ctx_last_launch": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "pgdto_ctx_autotune_save": (C.c_int, [_VP, C.c_char_p]),
+    "pgdto_ctx_autotune_load": (C.c_int, [_VP, C.c_char_p]),
     "pgdto_project": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), C.POINTER(Result), _VP]),
     "pgdto_project_async": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP]),
     "pgdto_project_noalloc": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _VP, _VP]),

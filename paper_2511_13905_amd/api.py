@@ -173,6 +173,19 @@ class Context:
         """pgdto_ctx_autotune: grid autotuning per shape class (returns the previous setting)."""
         return N.lib().pgdto_ctx_autotune(self.h, int(enable))
 
+    def autotune_save(self, path: str) -> int:
+        """pgdto_ctx_autotune_save: write the tuned grid choices to `path`."""
+        n = N.lib().pgdto_ctx_autotune_save(self.h, str(path).encode())
+        _check(min(n, 0), "pgdto_ctx_autotune_save")
+        return n
+
+    def autotune_load(self, path: str) -> int:
+        """pgdto_ctx_autotune_load: add the choices saved in `path` (0 if they
+        were measured on another device or library version)."""
+        n = N.lib().pgdto_ctx_autotune_load(self.h, str(path).encode())
+        _check(min(n, 0), "pgdto_ctx_autotune_load")
+        return n
+
     def last_launch(self):
         """(workgroups, tiles) of the last launch on this context."""
         g, t = C.c_int32(), C.c_int32()
@@ -218,7 +231,7 @@ class Context:
 
     # ------------------------------------------------------------ Alg. 3 step
     def _pgd_struct(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                    hyper, keep, copy_ok=True, eq=None, lam0=None):
+                    hyper, keep, copy_ok=True, eq=None, lam0=None, work=None):
         s, x, _A = problem_struct(kind, None, A, None, lo, hi, C, offsets, x if x is not None else
                                   torch.empty_like(rho), None, keep, copy_ok=copy_ok, eq=eq, lam0=lam0)
         a = N.PgdArgs()
@@ -232,6 +245,7 @@ class Context:
         a.g = keep.dbl(list(g))
         a.G = keep.dbl(list(G))
         a.t = int(t)
+        a.work = work.data_ptr() if work is not None else None
         for k, v in (hyper or {}).items():
             if k == "cg_rule" and isinstance(v, str):
                 v = N.CG_RULES[v]
@@ -239,13 +253,14 @@ class Context:
         return a, x
 
     def pgd_step(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf,
-                 offsets=None, x=None, params=None, stream=None, eq=None, lam0=None, **hyper):
+                 offsets=None, x=None, params=None, stream=None, eq=None, lam0=None, work=None, **hyper):
         """pgdto_pgd_step: one Alg. 3 body.  d is updated in place (d_{t-1} -> d_t);
         returns (rho_{t+1}, out dict).  lam0: warm start of the projection
-        (e.g. out["proj"]["lam"] of the previous step)."""
+        (e.g. out["proj"]["lam"] of the previous step); work: optional
+        compaction scratch of n elements (may be grad_prev's buffer)."""
         keep = _Keep()
         a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                hyper, keep, eq=eq, lam0=lam0)
+                                hyper, keep, eq=eq, lam0=lam0, work=work)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         out = N.PgdOut()
         st = N.lib().pgdto_pgd_step(self.h, C_byref(a), C_byref(p), C_byref(out), _stream(self.device, stream))
@@ -285,17 +300,17 @@ class Context:
             arr[i], _ = self._pgd_struct(s["kind"], s["A"], s["rho"], s.get("rho_prev"), s["grad"],
                                          s.get("grad_prev"), s["d"], s["g"], s["G"], s["t"], s["lo"], s["hi"],
                                          s.get("C", math.inf), s.get("offsets"), s["x"], hyper, keep,
-                                         copy_ok=False)
+                                         copy_ok=False, work=s.get("work"))
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         st = N.lib().pgdto_pgd_step_batch_async(self.h, arr, len(steps), C_byref(p), outs_buf.data_ptr(), int(slots),
                                                 _stream(self.device, stream))
         _check(st, "pgdto_pgd_step_batch_async")
 
     def pgd_step_async(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, out_buf,
-                       C=math.inf, offsets=None, x=None, params=None, stream=None, lam0=None, **hyper):
+                       C=math.inf, offsets=None, x=None, params=None, stream=None, lam0=None, work=None, **hyper):
         keep = _Keep()
         a, x = self._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                hyper, keep, lam0=lam0)
+                                hyper, keep, lam0=lam0, work=work)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         st = N.lib().pgdto_pgd_step_async(self.h, C_byref(a), C_byref(p), out_buf.data_ptr(),
                                           _stream(self.device, stream))
@@ -379,17 +394,17 @@ class Batch:
         return t.value
 
     def submit_pgd(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C=math.inf, offsets=None,
-                   x=None, params=None, lam0=None, **hyper) -> int:
+                   x=None, params=None, lam0=None, work=None, **hyper) -> int:
         """pgdto_batch_submit_pgd: one Algorithm 3 step as a served request
         (d is updated in place, rho_{t+1} lands in x).  A must already have
         16-byte aligned rows; the data must be complete when this is called."""
         keep = _Keep()
         a, x = self.ctx._pgd_struct(kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
-                                    hyper, keep, copy_ok=False, lam0=lam0)
+                                    hyper, keep, copy_ok=False, lam0=lam0, work=work)
         p = params if isinstance(params, N.Params) else make_params(**(params or {}))
         tk = C_u64()
         _check(N.lib().pgdto_batch_submit_pgd(self.h, C_byref(a), C_byref(p), C_byref(tk)), "pgdto_batch_submit_pgd")
-        self._live[tk.value] = (rho, A, x, rho_prev, grad, grad_prev, d)
+        self._live[tk.value] = (rho, A, x, rho_prev, grad, grad_prev, d, work)
         return tk.value
 
     def poll_pgd(self, ticket, wait=False):
@@ -441,11 +456,45 @@ TUNE_SHAPES = 5                                   # PGDTO_TUNE_SHAPES
 TUNE_SLOTS = [4 << c for c in range(TUNE_SHAPES)]   # slot counts of the candidates
 
 
-def batch_autotune(ctx: Context, problems, count: int = 64, params=None):
+def _shape_key(ctx, problems, count):
+    """Cache key of an executor-shape choice: library version, device, and the
+    kinds, sizes and rows of the samples."""
+    props = torch.cuda.get_device_properties(ctx.device)
+    dev = f"{getattr(props, 'gcnArchName', props.name)}-{props.multi_processor_count}cu"
+    sig = ";".join(f"{k}:{y.numel() if y is not None else x.numel()}:{A.shape[0] if A.dim() > 1 else 1}"
+                   for (k, y, A, b, lo, hi, C_pen, offsets, x) in problems)
+    return f"v{N.lib().pgdto_version()}|{dev}|{count}|{sig}"
+
+
+def batch_autotune(ctx: Context, problems, count: int = 64, params=None, cache: str | None = None):
     """pgdto_batch_autotune: the executor shape (slots, workgroups per slot)
     with the highest throughput on `count` requests drawn round-robin from
     `problems` (a list of (kind, y, A, b, lo, hi, C, offsets, x) tuples whose
-    tensors are ready), plus the wall time in ms of every candidate shape."""
+    tensors are ready), plus the wall time in ms of every candidate shape.
+    cache: a JSON file of earlier choices, keyed by library version, device
+    and the samples' kinds and sizes; a hit returns the stored shape and
+    times without running the candidates, a miss tunes and stores."""
+    import json
+    import os
+    key = _shape_key(ctx, problems, count) if cache else None
+    store = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            store = json.load(f)
+        if key in store:
+            hit = store[key]
+            return (int(hit["slots"]), int(hit["wg_per_slot"])), [float(t) for t in hit["times_ms"]]
+    shape, times = _batch_autotune_run(ctx, problems, count, params)
+    if cache:
+        store[key] = {"slots": shape[0], "wg_per_slot": shape[1], "times_ms": times}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(store, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return shape, times
+
+
+def _batch_autotune_run(ctx: Context, problems, count: int, params):
     keep = _Keep()
     arr = (N.Problem * len(problems))()
     for i, (kind, y, A, b, lo, hi, C_pen, offsets, x) in enumerate(problems):

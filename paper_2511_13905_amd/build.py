@@ -8,9 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpgdto.so")
-ORACLE_C = os.path.join(ROOT, "oracle")
 
 SOURCES = ["pgdto_kernels.hip", "pgdto_host.cpp", "pgdto_serve.cpp", "pgdto_server.cpp", "pgdto_many.cpp"]
 
@@ -26,28 +24,50 @@ def hipcc() -> str:
     return cand
 
 
-def build(verbose: bool = False) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# built as usual: every -fsanitize= applies to the host pass only).
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined"]
+LIB_SAN = os.path.join(HERE, "libpgdto_san.so")
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime to preload into an uninstrumented python."""
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    cands = sorted(glob.glob(os.path.join(root, "lib", "clang", "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    cands += sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return cands[-1] if cands else ""
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source and link libpgdto.so (sanitize: libpgdto_san.so
+    with the host code instrumented, for the CPU test suite)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
             continue
         obj = os.path.join(bdir, src + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, "-x", "hip", "-c", path, "-o", obj]
+        flags = [f for f in HIP_FLAGS if f != "-O3"] + SANITIZE_FLAGS if sanitize else HIP_FLAGS
+        cmd = [hipcc(), *flags, "-x", "hip", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    lib = LIB_SAN if sanitize else LIB
+    tmp = lib + ".tmp"
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"] if sanitize else []
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *san, *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

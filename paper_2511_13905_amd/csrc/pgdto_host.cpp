@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -29,6 +30,7 @@ extern "C" void pgdto_params_default(pgdto_params* p) {
   p->stage1 = 1;
   p->c1 = 1e-4;
   p->c2 = 0.9;
+  p->compact = 0;
 }
 
 extern "C" void pgdto_pgd_args_default(pgdto_pgd_args* a) {
@@ -182,6 +184,7 @@ int validate_params(const pgdto_params* p) {
   if (p->search != PGDTO_SEARCH_NEWTON && p->search != PGDTO_SEARCH_BISECT) return PGDTO_ERR_ARG;
   if (p->ncp != PGDTO_NCP_CONTINUOUS && p->ncp != PGDTO_NCP_PAPER) return PGDTO_ERR_ARG;
   if (!(p->c1 > 0.0 && p->c1 < 1.0 && p->c2 > p->c1 && p->c2 < 1.0)) return PGDTO_ERR_ARG;
+  if (p->compact != 0 && p->compact != 1) return PGDTO_ERR_ARG;
   return PGDTO_OK;
 }
 
@@ -256,6 +259,8 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   d.search = pp->search;
   d.ncp = pp->ncp;
   d.stage1 = pp->stage1 ? 1 : 0;
+  d.compact = pp->compact;
+  d.cbuf = pr->x;                      // a projection's x is free until its final pass
   for (int j = 0; j < pr->m; ++j) d.b[j] = pr->b[j];
 
   // segments
@@ -362,6 +367,17 @@ int fill_pgd(const pgdto_pgd_args* a, Desc& d) {
   for (const void* p : ins)
     if (p && (overlaps(pr->x, bytes, p, bytes) || overlaps(a->dir, bytes, p, bytes))) return PGDTO_ERR_ARG;
   if (overlaps(pr->x, bytes, a->dir, bytes)) return PGDTO_ERR_ARG;
+  if (a->work) {
+    // compaction scratch: may reuse rho_prev / grad_prev (read in the first pass only)
+    if (!aligned16(a->work)) return PGDTO_ERR_ARG;
+    const size_t abytes = pr->kind == PGDTO_INDEPENDENT
+                              ? bytes : ((size_t)(pr->m - 1) * (size_t)d.lda + (size_t)pr->n) * esz;
+    const void* used[] = {pr->x, a->dir, a->rho, a->grad};
+    for (const void* p : used)
+      if (overlaps(a->work, bytes, p, bytes)) return PGDTO_ERR_ARG;
+    if (overlaps(a->work, bytes, pr->A, abytes)) return PGDTO_ERR_ARG;
+  }
+  d.cbuf = a->work;                    // x holds rho~ during the search
   double viol = 0.0;
   for (int j = 0; j < pr->m; ++j) {
     if (!isfinite(a->g[j]) || !isfinite(a->G[j])) return PGDTO_ERR_ARG;
@@ -459,6 +475,58 @@ extern "C" int pgdto_ctx_autotune(pgdto_ctx* c, int enable) {
   c->autotune = enable ? 1 : 0;
   if (enable < 0) c->tuned_grid.clear();
   return prev;
+}
+
+// Persisted autotuner choices: a header line naming the file format, the
+// library version and the device (its architecture and compute units), then
+// one "key grid" line per shape class.  A file written for another device or
+// library version is ignored on load, so a cache never carries a choice to
+// hardware it was not measured on.
+static int device_tag(int device, char* out, size_t cap) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PGDTO_ERR_HIP;
+  snprintf(out, cap, "%s-%dcu", prop.gcnArchName, prop.multiProcessorCount);
+  for (char* p = out; *p; ++p)
+    if (*p == ' ' || *p == '\n') *p = '_';
+  return PGDTO_OK;
+}
+
+extern "C" int pgdto_ctx_autotune_save(pgdto_ctx* c, const char* path) {
+  if (!c || !path) return PGDTO_ERR_ARG;
+  char tag[256];
+  const int st = device_tag(c->device, tag, sizeof(tag));
+  if (st != PGDTO_OK) return st;
+  FILE* f = fopen(path, "w");
+  if (!f) return PGDTO_ERR_ARG;
+  fprintf(f, "pgdto-grid-tune %d %s\n", PGDTO_VERSION, tag);
+  int n = 0;
+  for (const auto& kv : c->tuned_grid) {
+    fprintf(f, "%llu %d\n", (unsigned long long)kv.first, kv.second);
+    ++n;
+  }
+  return fclose(f) == 0 ? n : PGDTO_ERR_ARG;
+}
+
+extern "C" int pgdto_ctx_autotune_load(pgdto_ctx* c, const char* path) {
+  if (!c || !path) return PGDTO_ERR_ARG;
+  char tag[256], ftag[256];
+  int st = device_tag(c->device, tag, sizeof(tag));
+  if (st != PGDTO_OK) return st;
+  FILE* f = fopen(path, "r");
+  if (!f) return PGDTO_ERR_ARG;
+  int ver = 0;
+  int n = 0;
+  if (fscanf(f, "pgdto-grid-tune %d %255s", &ver, ftag) == 2 && ver == PGDTO_VERSION && strcmp(tag, ftag) == 0) {
+    unsigned long long key;
+    int grid;
+    while (fscanf(f, "%llu %d", &key, &grid) == 2) {
+      if (grid < 1 || grid > GMAX) continue;
+      c->tuned_grid[(uint64_t)key] = grid;
+      ++n;
+    }
+  }
+  fclose(f);
+  return n;
 }
 
 extern "C" int pgdto_ctx_last_launch(pgdto_ctx* c, int32_t* grid, int32_t* tiles) {

@@ -41,12 +41,14 @@ struct Desc {
   const void* A;
   void* x;
   uint32_t* free_mask;
+  void* cbuf;            // free-set compaction scratch, n elements of the stream dtype (x, or the
+                         // Algorithm 3 step's work buffer); NULL: no compaction
   double lo, hi, kappa;
   double auto_tau;       // > 0: kappa = auto_tau / (largest breakpoint), set after the zero pass
   uint64_t eq_mask;      // bit j: row / block j is an equality a_j.x = b_j
   uint64_t door_wait;    // longest wait of the arrival door for the grid (100 MHz ticks)
   double tol_b, tol_n, c1, c2;
-  int32_t max_search, max_newton, max_ls, search, ncp, stage1;
+  int32_t max_search, max_newton, max_ls, search, ncp, stage1, compact;
   double b[PGDTO_MAX_BLOCKS];          // right-hand sides (pgd: G - g)
   double lam0[PGDTO_MAX_BLOCKS];       // warm start (warm != 0)
   int32_t warm;

@@ -561,6 +561,7 @@ struct Search {
   double trial[PGDTO_MAX_BLOCKS][NT];
   int32_t state[PGDTO_MAX_BLOCKS], outcome[PGDTO_MAX_BLOCKS], npass[PGDTO_MAX_BLOCKS];
   int32_t shrunk[PGDTO_MAX_BLOCKS];
+  int32_t cmode[PGDTO_MAX_BLOCKS];  // free-set compaction: 0 not yet, 1 in the coming pass, 2 done
 };
 
 __device__ __forceinline__ bool inside(double v, double lo, double hi) { return v > lo && v < hi; }
@@ -578,19 +579,23 @@ __device__ __forceinline__ void search_pick(Search& S, int s, int mode, bool lea
   const double nhi = S.shi[s] > 0.0 ? hi + S.fhi[s] / S.shi[s] : NAN;
   // First trial: the Newton point from the lower end (the tangent of the
   // piecewise-linear dual there), else the secant, else the midpoint.
-  // Second trial: the midpoint when the previous pass did not halve the
-  // bracket (a bisection step, so the bracket at least halves every second
-  // pass); otherwise the Newton point from the upper end.  lean (the 1-D
-  // searches): while the upper end has no slope yet, twice the Newton step
-  // from the lower end instead -- the dual is typically convex there, so the
-  // tangent from below undershoots and the doubled step brackets the root
-  // from above, which lets the next Newton/secant steps close in from both
-  // sides (6 passes instead of 8 on the 256x128x128 compliance row).
+  // Second trial: the Newton point from the upper end when the previous
+  // pass halved the bracket.  lean (the 1-D searches): otherwise, and while
+  // the upper end has no slope yet, twice the Newton step from the lower end
+  // -- the dual is typically convex there, so the tangent from below
+  // undershoots and the doubled step brackets the root from above, which
+  // lets the next steps close in from both sides and narrows the bracket
+  // early (the free-set compaction below needs a narrow bracket).  Without
+  // lean, a pass that did not halve the bracket is followed by a midpoint.
   double t0 = inside(nlo, lo, hi) ? nlo : (inside(sec, lo, hi) ? sec : mid);
   if (!inside(t0, lo, hi)) t0 = mid;
   const double ext = lo + 2.0 * (nlo - lo);
+  const bool doubled = lean && inside(nlo, lo, hi) && inside(ext, lo, hi);
   double t1;
-  if (!S.shrunk[s]) t1 = mid;
+  // a bracket that did not halve: the doubled Newton step from below (the
+  // distance covered from below at least doubles every pass), else the
+  // midpoint (the bracket halves)
+  if (!S.shrunk[s]) t1 = doubled ? ext : mid;
   else if (inside(nhi, lo, hi) && nhi != t0) t1 = nhi;
   else if (lean && inside(nlo, lo, hi) && inside(ext, lo, hi)) t1 = ext;
   else if (inside(sec, lo, hi) && sec != t0) t1 = sec;
@@ -789,11 +794,94 @@ __device__ __forceinline__ void pgd_scalars(const Desc& d, const double* v, PgdS
   o.beta = beta;
 }
 
+// ------------------------------------------------------------------ free-set compaction
+// Once a row's bracket [bl, bh] is narrow, an element whose state (below,
+// inside or above the box) is the same at both ends keeps that state for
+// every later trial multiplier in the bracket (z = y - lam a is monotone in
+// lam, and so is its correctly rounded fma): its term of a.x(lam) is a
+// constant (a lo, a hi) or linear in lam (a y - lam a^2).  The compaction
+// pass folds those into per-tile sums S0 (the constants and a y) and Q
+// (a^2 of the free ones) and copies the other ("undecided") elements' (y, a)
+// pairs to scratch; later passes of the tile then evaluate
+//   a.x(lam) = S0 - lam Q + sum over the undecided pairs,
+//   slope     = Q + sum of a^2 over the undecided pairs that are free,
+// reading a few percent of the bytes.  Only whole interior tiles take part,
+// and whether a tile is compacted depends on its data alone (not on the
+// workgroups or the route), so every route still gives the same bits.
+// Each wave compacts its own share of the tile (tile_elems / NWAVE elements,
+// so at most half as many pairs fit its region of the scratch), with a
+// wave-level scan and no workgroup barrier; a later pass reduces a
+// compacted tile with one wave, so a workgroup evaluates up to NWAVE of its
+// compacted tiles at once, each in one round trip to memory.  Per-tile
+// metadata sits in rows of the partial-sum table that the 1-D passes do not
+// use: per wave, the pairs kept (or -1 when its region overflowed, which
+// keeps the tile whole), the folded constant terms S0 and the folded slope Q.
+constexpr int META_ROWS = 3 * NWAVE;
+constexpr int META_ROW = VMAX - META_ROWS;
+constexpr int NV_SEARCH = 2 * NT + 1;      // per trial a.x and slope, then the pairs kept
+
+__device__ __forceinline__ double* meta_row(const Desc& d, int r) {
+  return d.part + (size_t)(META_ROW + r) * TILES_PAD;      // buffer 0
+}
+
+// Element state at multiplier lam: 0 below the box, 1 inside, 2 above.
+__device__ __forceinline__ int elem_state(double yq, double av, double lam, double lo, double hi) {
+  const double z = fma(-lam, av, yq);
+  return z < lo ? 0 : (z > hi ? 2 : 1);
+}
+
+// A kept (y, a) pair.  Only the workgroup that owns the tile writes and
+// later reads it (the tile-to-workgroup map is fixed for a launch), on the
+// same CU: plain stores and loads, one 8- or 16-byte access per pair.
+template <typename T>
+__device__ __forceinline__ void put_pair(T* dst, int64_t j, T y, T a) {
+  typedef T P2 __attribute__((ext_vector_type(2)));
+  *reinterpret_cast<__attribute__((address_space(1))) P2*>(gptr_w(dst) + 2 * j) = P2{y, a};
+}
+template <typename T>
+__device__ __forceinline__ void get_pair(const T* src, int64_t j, T& y, T& a) {
+  typedef T P2 __attribute__((ext_vector_type(2)));
+  const P2 v = *reinterpret_cast<const __attribute__((address_space(1))) P2*>(gptr(src) + 2 * j);
+  y = v.x;
+  a = v.y;
+}
+
+// One vector slot per lane, called by every lane of the wave together: the
+// slot's undecided elements (bits of ub) are appended at the wave's running
+// count `run` in (lane, element) order; `ok` turns false for the wave when
+// its capacity `capw` would be exceeded.
+template <typename T>
+__device__ __forceinline__ void compact_slot(const T* yv, const T* av, uint32_t ub, T* dst, int64_t capw,
+                                             int64_t& run, bool& ok) {
+  constexpr int V = VT<T>::N;
+  const int lane = threadIdx.x & 63;
+  const int c = __popc(ub);
+  int incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  const int total = __shfl(incl, 63, 64);
+  if (ok && run + total <= capw) {
+    int64_t pos = run + (incl - c);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      if ((ub >> q) & 1u) put_pair<T>(dst, pos++, yv[q], av[q]);
+    }
+  }
+  if (run + total > capw) ok = false;
+  run += total;
+}
+
 // ================================================================== 1-D kernel
 // SINGLE and INDEPENDENT: one bracket search per segment, all segments in
 // lockstep passes (Alg. 1; Sec. 3.2.2 for independent blocks).
 
 struct Sh1D {
+  uint8_t cflag[TILES_PAD];       // per local tile in a search pass: 1 = compacted, evaluated by one wave
+  double ncomp[PGDTO_MAX_BLOCKS]; // pairs kept by the compaction per segment (-1: none ran)
+  int32_t npc[PGDTO_MAX_BLOCKS];  // search passes that streamed only the kept pairs
   double tot[PGDTO_MAX_BLOCKS * 9];
   double amax[PGDTO_MAX_BLOCKS];  // max_i |a_i| per segment (zero pass)
   double red[NWAVE * BLOCK];
@@ -807,9 +895,9 @@ struct Sh1D {
 
 // SU: vector slots in flight per stream in the streaming passes.  EQ: the
 // instance has rows held at equality (the zero pass adds the opposite
-// direction's bracket); a separate instantiation, so that the common case
-// keeps its register allocation.
-template <typename T, bool EQ = false, int SU = 2>
+// direction's bracket); CP: the free-set compaction is on.  Separate
+// instantiations, so that the common case keeps its register allocation.
+template <typename T, bool EQ = false, bool CP = false, int SU = 2>
 __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   constexpr int V = VT<T>::N;
   constexpr int SU1 = SU > 2 ? SU / 2 : 1;     // for the 3- to 5-stream passes
@@ -830,12 +918,16 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     sh.sg[s] = 1.0;
     sh.S.state[s] = SEG_DONE; sh.S.lam[s] = 0.0; sh.S.npass[s] = 0; sh.S.width[s] = 0.0;
     sh.S.outcome[s] = PGDTO_INACTIVE; sh.S.scale[s] = 1.0; sh.S.ssat[s] = 0.0;
-    sh.S.err[s] = 0.0; sh.S.slope[s] = 0.0; sh.amax[s] = 0.0;
+    sh.S.err[s] = 0.0; sh.S.slope[s] = 0.0; sh.amax[s] = 0.0; sh.S.cmode[s] = 0; sh.ncomp[s] = -1.0; sh.npc[s] = 0;
   }
   __syncthreads();
 
   int buf = 0;
   const T* A = (const T*)d.A;
+  // CP: the instantiation with the free-set compaction (a request asks for
+  // it with compact != 0 and scratch); without it every compaction branch
+  // folds away and the kernel keeps the register allocation of the plain search
+  T* CB = CP ? (T*)d.cbuf : nullptr;
   T* X = (T*)d.x;
   const T* Y = d.pgd ? (const T*)d.x : (const T*)d.y;
 
@@ -947,6 +1039,25 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     trace_put(d, pass_no, 0, ((uint64_t)ph << 56) | (t_pass0 & 0x00ffffffffffffffull));
     int nv = 0;
     uint64_t maxmask = 0;
+    // compacted tiles of this workgroup (every wave kept its pairs): they are
+    // evaluated one per wave after the loop below
+    const int nloc = wid < d.ntiles ? (d.ntiles - wid + G - 1) / G : 0;
+    if (ph == PH_SEARCH && CB != nullptr) {
+      for (int k = tid; k < nloc; k += BLOCK) {
+        const int tile = wid + k * G;
+        const TileGeom g = tile_geom<T>(d, tile);
+        bool f = g.interior && sh.S.cmode[g.seg] == 2 && sh.S.state[g.seg] == SEG_SEARCH;
+        if (f) {
+          double c[NWAVE];
+#pragma unroll
+          for (int w = 0; w < NWAVE; ++w) c[w] = fetch_published(meta_row(d, w) + tile);
+#pragma unroll
+          for (int w = 0; w < NWAVE; ++w) f = f && c[w] >= 0.0;
+        }
+        sh.cflag[k] = f ? 1 : 0;
+      }
+      __syncthreads();
+    }
 
     for (int tile = wid; tile < d.ntiles; tile += G) {
       const TileGeom g = tile_geom<T>(d, tile);
@@ -1114,7 +1225,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         };
         zero_tile();
       } else if (ph == PH_SEARCH) {
-        nv = 2 * NT; maxmask = 0;
+        nv = NV_SEARCH; maxmask = 0;
         if (sh.S.state[s] == SEG_DONE) continue;      // finished segments are not streamed
         const double sgs = EQ ? sh.sg[s] : 1.0;
         const double l0 = sgs * sh.S.trial[s][0], l1 = sgs * sh.S.trial[s][1];
@@ -1159,10 +1270,85 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             });
           }
         };
-        if (l1 == l1) run(std::true_type{}); else run(std::false_type{});
-        const double acc[2 * NT] = {cs[0][0] + cs[1][0], (double)sl[0][0] + (double)sl[1][0],
-                                    cs[0][1] + cs[1][1], (double)sl[0][1] + (double)sl[1][1]};
-        block_to_part<2 * NT>(acc, nv, maxmask, sh.red, pb, tile);
+        double kept = 0.0;                        // pairs this thread's wave kept (compaction pass)
+        const int cm = (CB != nullptr && g.interior) ? sh.S.cmode[s] : 0;
+        if (cm == 2 && sh.cflag[(tile - wid) / G]) continue;     // evaluated by one wave below
+        if (cm == 1) {
+          // this pass evaluates the trials as usual and compacts the tile
+          // against the bracket it starts from (every later trial lies in it);
+          // wave w owns elements of threads [64 w, 64 w + 64) and the region
+          // [w E / NWAVE, (w + 1) E / NWAVE) of the tile's scratch, E = tile_elems
+          const double ba = sgs * sh.S.lo[s], bb = sgs * sh.S.hi[s];
+          const double bl = fmin(ba, bb), bh = fmax(ba, bb);
+          const int64_t seg_el = d.tile_elems / NWAVE;
+          T* dst = CB + g.ts + (int64_t)(tid >> 6) * seg_el;
+          int64_t crun = 0;
+          bool cok = true;
+          double s0 = 0.0, qq = 0.0;
+          auto slot_c = [&](const T* yv, const T* av, auto two_c) __attribute__((always_inline)) {
+            constexpr bool TWO = decltype(two_c)::value;
+            uint32_t ub = 0u;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+              const double yq = f64(yv[q]), aq = f64(av[q]);
+              const S a2 = (S)av[q] * (S)av[q];
+              const double z0 = fma(-l0, aq, yq);
+              const double x0 = fmin(fmax(z0, lo), hi);
+              cs[q & 1][0] = fma(aq, x0, cs[q & 1][0]);
+              sl[q & 1][0] += (x0 == z0) ? a2 : (S)0;
+              if constexpr (TWO) {
+                const double z1 = fma(-l1, aq, yq);
+                const double x1 = fmin(fmax(z1, lo), hi);
+                cs[q & 1][1] = fma(aq, x1, cs[q & 1][1]);
+                sl[q & 1][1] += (x1 == z1) ? a2 : (S)0;
+              }
+              // branch-free: decided elements fold into s0 (and qq when free)
+              const int sa = elem_state(yq, aq, bl, lo, hi), sb = elem_state(yq, aq, bh, lo, hi);
+              const bool dec = sa == sb, fr = dec && sa == 1;
+              const double term = fr ? yq : (sa == 0 ? lo : hi);
+              s0 = dec ? fma(aq, term, s0) : s0;
+              qq = fr ? fma(aq, aq, qq) : qq;
+              ub |= dec ? 0u : (1u << q);
+            }
+            compact_slot<T>(yv, av, ub, dst, seg_el / 2, crun, cok);
+          };
+          auto run_k = [&](auto two_c) __attribute__((always_inline)) {
+            if (tile == wid && resident) {
+#pragma unroll 1
+              for (int k = 0; k < RS; ++k) slot_c(ry[k], ra[k], two_c);
+            } else {
+              // an interior tile: every slot whole (nsweep even), two slots in flight
+              const int64_t base = (g.p0 + (int64_t)tid) * V;
+              for (int k0 = 0; k0 < g.nsweep; k0 += 2) {
+                T b[2][2][V];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                  const int64_t e0 = base + (int64_t)(k0 + u) * (BLOCK * V);
+                  ld_vec_whole<T>(gptr(Y), e0, b[u][0]);
+                  ld_vec_whole<T>(gptr(A), e0, b[u][1]);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) slot_c(b[u][0], b[u][1], two_c);
+              }
+            }
+          };
+          if (l1 == l1) run_k(std::true_type{}); else run_k(std::false_type{});
+          // the wave's folded sums and count (fixed butterfly order)
+          s0 = wave_sum(s0);
+          qq = wave_sum(qq);
+          if ((tid & 63) == 0) {
+            const int w = tid >> 6;
+            publish(meta_row(d, w) + tile, cok ? (double)crun : -1.0);
+            publish(meta_row(d, NWAVE + w) + tile, s0);
+            publish(meta_row(d, 2 * NWAVE + w) + tile, qq);
+            kept = cok ? (double)crun : 0.0;
+          }
+        } else {
+          if (l1 == l1) run(std::true_type{}); else run(std::false_type{});
+        }
+        const double acc[NV_SEARCH] = {cs[0][0] + cs[1][0], (double)sl[0][0] + (double)sl[1][0],
+                                       cs[0][1] + cs[1][1], (double)sl[0][1] + (double)sl[1][1], kept};
+        block_to_part<NV_SEARCH>(acc, nv, maxmask, sh.red, pb, tile);
       } else {  // PH_FINAL
         nv = 4; maxmask = 0;
         double acc[4] = {0, 0, 0, 0};
@@ -1260,8 +1446,87 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
       }
     }
+    if (ph == PH_SEARCH && CB != nullptr) {
+      // one wave per compacted tile: its folded sums plus the kept pairs, the
+      // pairs of the tile's NWAVE regions taken in order, 8 per lane in flight
+      using S = typename std::conditional<sizeof(T) == 4, float, double>::type;
+      const int w = tid >> 6, lane = tid & 63;
+      const int64_t seg_el = d.tile_elems / NWAVE;
+      int rank = 0;
+      for (int k = 0; k < nloc; ++k) {
+        if (!sh.cflag[k]) continue;
+        if ((rank++ % NWAVE) != w) continue;
+        const int tile = wid + k * G;
+        const TileGeom g = tile_geom<T>(d, tile);
+        const int s = g.seg;
+        const double sgs = EQ ? sh.sg[s] : 1.0;
+        const double l0 = sgs * sh.S.trial[s][0], l1 = sgs * sh.S.trial[s][1];
+        const bool two = (l1 == l1);
+        const double mv = lane < META_ROWS ? fetch_published(meta_row(d, lane) + tile) : 0.0;
+        int64_t pre[NWAVE + 1];
+        pre[0] = 0;
+        double S0 = 0.0, Q = 0.0;
+#pragma unroll
+        for (int v = 0; v < NWAVE; ++v) pre[v + 1] = pre[v] + (int64_t)__shfl(mv, v, 64);
+#pragma unroll
+        for (int v = 0; v < NWAVE; ++v) S0 += __shfl(mv, NWAVE + v, 64);
+#pragma unroll
+        for (int v = 0; v < NWAVE; ++v) Q += __shfl(mv, 2 * NWAVE + v, 64);
+        const T* base = CB + g.ts;
+        double c0 = 0.0, c1 = 0.0;
+        S f0 = 0, f1 = 0;
+        constexpr int PB = 8;
+        for (int64_t j0 = 0; j0 < pre[NWAVE]; j0 += 64 * PB) {
+          T yy[PB], aa[PB];
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int64_t j = j0 + (int64_t)u * 64 + lane;
+            yy[u] = (T)0;
+            aa[u] = (T)0;
+            // the region holding pair j (constant indices keep pre in registers)
+            int v = 0;
+            int64_t pv = 0;
+#pragma unroll
+            for (int r = 1; r < NWAVE; ++r) {
+              const bool ge = j >= pre[r];
+              v += ge ? 1 : 0;
+              pv = ge ? pre[r] : pv;
+            }
+            if (j < pre[NWAVE]) get_pair<T>(base + (int64_t)v * seg_el, j - pv, yy[u], aa[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const double yq = f64(yy[u]), av = f64(aa[u]);
+            const S a2 = (S)aa[u] * (S)aa[u];
+            const double z0 = fma(-l0, av, yq);
+            const double x0 = fmin(fmax(z0, lo), hi);
+            c0 = fma(av, x0, c0);
+            f0 += (x0 == z0) ? a2 : (S)0;
+            if (two) {
+              const double z1 = fma(-l1, av, yq);
+              const double x1 = fmin(fmax(z1, lo), hi);
+              c1 = fma(av, x1, c1);
+              f1 += (x1 == z1) ? a2 : (S)0;
+            }
+          }
+        }
+        // padding pairs (0, 0) add exactly nothing: z = 0 is clipped (x = lo
+        // or 0 times a = 0) and the slope term is a^2 = 0
+        c0 = wave_sum(c0);
+        c1 = wave_sum(c1);
+        const double g0 = wave_sum((double)f0), g1 = wave_sum((double)f1);
+        if (lane == 0) {
+          publish(&pb[0 * TILES_PAD + tile], c0 + fma(-l0, Q, S0));
+          publish(&pb[1 * TILES_PAD + tile], g0 + Q);
+          publish(&pb[2 * TILES_PAD + tile], two ? c1 + fma(-l1, Q, S0) : 0.0);
+          publish(&pb[3 * TILES_PAD + tile], two ? g1 + Q : 0.0);
+          publish(&pb[4 * TILES_PAD + tile], 0.0);
+        }
+      }
+      wait_own_stores();
+    }
     if (ph == PH_ZERO) { nv = EQ ? 9 : 7; maxmask = (EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2)) | (1ull << (nv - 1)); }
-    else if (ph == PH_SEARCH) { nv = 2 * NT; maxmask = 0; }
+    else if (ph == PH_SEARCH) { nv = NV_SEARCH; maxmask = 0; }
     else { nv = 4; maxmask = 0; }
 
     trace_put(d, pass_no, 1, clk());
@@ -1311,8 +1576,16 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       for (int s = tid; s < d.nseg; s += BLOCK) {
         if (sh.S.state[s] != SEG_SEARCH) continue;
         const double sg = EQ ? sh.sg[s] : 1.0;      // a sign-flipped row sees -a.x and -b
-        search_update(sh.S, s, sg * sh.tot[s * 4 + 0], sg * sh.tot[s * 4 + 2], sh.tot[s * 4 + 1],
-                      sh.tot[s * 4 + 3], sg * sh.bs[s], kappa, d.tol_n, d.tol_b, d.max_search, d.search, true);
+        const double* t = &sh.tot[s * NV_SEARCH];
+        if (sh.S.cmode[s] == 2) sh.npc[s] += 1;
+        search_update(sh.S, s, sg * t[0], sg * t[2], t[1], t[3], sg * sh.bs[s], kappa, d.tol_n, d.tol_b,
+                      d.max_search, d.search, true);
+        // free-set compaction: done in the pass just finished, or due in the
+        // next one once the bracket lies within 25% of its upper end
+        if (sh.S.cmode[s] == 1) { sh.S.cmode[s] = 2; sh.ncomp[s] = t[4]; }
+        else if (sh.S.cmode[s] == 0 && d.compact && d.cbuf && sh.S.state[s] == SEG_SEARCH &&
+                 sh.S.hi[s] - sh.S.lo[s] <= 0.25 * fabs(sh.S.hi[s]))
+          sh.S.cmode[s] = 1;
       }
       __syncthreads();
       if (tid == 0) {
@@ -1342,7 +1615,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         __syncthreads();
         if (tid == 0) {
           int worst = PGDTO_INACTIVE, anyact = 0, np = 0;
-          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0, rmax = 0.0, xerr = 0.0;
+          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0, rmax = 0.0, xerr = 0.0, ncomp = -1.0;
+          int npc = 0;
           for (int s = 0; s < d.nseg; ++s) {
             if (severity(sh.S.outcome[s]) > severity(worst)) worst = sh.S.outcome[s];
             anyact |= (sh.S.outcome[s] != PGDTO_INACTIVE);
@@ -1354,7 +1628,11 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             nfree += sh.tot[s * 4 + 1];
             diff2 += sh.tot[s * 4 + 2];
             xx += sh.tot[s * 4 + 3];
+            if (sh.ncomp[s] >= 0.0) ncomp = fmax(ncomp, 0.0) + sh.ncomp[s];
+            npc = max(npc, sh.npc[s]);
           }
+          R->n_compact = (int64_t)ncomp;
+          R->passes_compacted = npc;
           R->outcome = worst;
           R->error = 0;
           R->path = anyact ? 1 : 0;
@@ -1482,7 +1760,7 @@ __device__ __forceinline__ bool enter_launch(Desc& sd, int32_t* late_sh) {
   return *late_sh == 0;
 }
 
-template <typename T, bool EQ>
+template <typename T, bool EQ, bool CP>
 __global__ __launch_bounds__(BLOCK, 2) void k_solve_1d(const Desc) {
   __shared__ Sh1D sh;
   __shared__ Desc sd;
@@ -1490,7 +1768,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_solve_1d(const Desc) {
   load_desc(sd);
   if (!enter_launch(sd, &late)) return;
   clear_mask_tiles<T>(sd);
-  solve_1d<T, EQ>(sh, sd);
+  solve_1d<T, EQ, CP>(sh, sd);
 }
 
 // ================================================================== coupled kernel
@@ -2301,6 +2579,8 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           R->m = M;
           R->n_free = (int64_t)t[M];
           R->res_inf = rmax;
+          R->n_compact = -1;                       // the coupled path does not compact
+          R->passes_compacted = 0;
           R->x_err = xerr + half_ulp(fmax(fabs(lo), fabs(hi)), sizeof(T) == 4);
           double wmax = 0.0;
           for (int j = 0; j < M; ++j) wmax = fmax(wmax, sh.S.width[j]);
@@ -2367,8 +2647,8 @@ union ShSrv {
 __shared__ ShSrv srv_sh;
 __shared__ Desc srv_sd;
 
-template <bool EQ>
-__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ>(srv_sh.s1, srv_sd); }
+template <bool EQ, bool CP>
+__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ, CP>(srv_sh.s1, srv_sd); }
 template <int M>
 __device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd); }
 
@@ -2465,10 +2745,13 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
         case 7: srv_solve_coupled<7>(); break;
         default: srv_solve_coupled<8>(); break;
       }
-    } else if (srv_sd.eq_mask) {
-      srv_solve_1d<true>();
     } else {
-      srv_solve_1d<false>();
+      const bool cp = srv_sd.compact && srv_sd.cbuf;
+      if (srv_sd.eq_mask) {
+        if (cp) srv_solve_1d<true, true>(); else srv_solve_1d<true, false>();
+      } else {
+        if (cp) srv_solve_1d<false, true>(); else srv_solve_1d<false, false>();
+      }
     }
     __syncthreads();
     if (vb == 0 && threadIdx.x == 0) {
@@ -2535,10 +2818,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
         case 7: srv_solve_coupled<7>(); break;
         default: srv_solve_coupled<8>(); break;
       }
-    } else if (srv_sd.eq_mask) {
-      srv_solve_1d<true>();
     } else {
-      srv_solve_1d<false>();
+      const bool cp = srv_sd.compact && srv_sd.cbuf;
+      if (srv_sd.eq_mask) {
+        if (cp) srv_solve_1d<true, true>(); else srv_solve_1d<true, false>();
+      } else {
+        if (cp) srv_solve_1d<false, true>(); else srv_solve_1d<false, false>();
+      }
     }
     __syncthreads();
   }
@@ -2568,16 +2854,26 @@ static const void* coupled_fn(int m) {
   }
 }
 
-static const void* kernel_fn(int kind, int dtype, int m, bool eq) {
+template <typename T>
+static const void* solve_1d_fn(bool eq, bool cp) {
+  if (eq) return cp ? (const void*)k_solve_1d<T, true, true> : (const void*)k_solve_1d<T, true, false>;
+  return cp ? (const void*)k_solve_1d<T, false, true> : (const void*)k_solve_1d<T, false, false>;
+}
+
+static const void* kernel_fn(int kind, int dtype, int m, bool eq, bool cp) {
   if (kind == PGDTO_COUPLED) return dtype == PGDTO_F32 ? coupled_fn<float>(m) : coupled_fn<double>(m);
-  if (dtype == PGDTO_F32) return eq ? (const void*)k_solve_1d<float, true> : (const void*)k_solve_1d<float, false>;
-  return eq ? (const void*)k_solve_1d<double, true> : (const void*)k_solve_1d<double, false>;
+  return dtype == PGDTO_F32 ? solve_1d_fn<float>(eq, cp) : solve_1d_fn<double>(eq, cp);
 }
 
 int max_coresident(int kind, int dtype, int m, int device) {
   int nb = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_fn(kind, dtype, m, false), BLOCK, 0) != hipSuccess)
+  // the plain and the compaction instantiations of a kernel fit alike (both
+  // take at most 256 VGPRs); the smaller count of the two is used
+  int nb2 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_fn(kind, dtype, m, false, false), BLOCK, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, kernel_fn(kind, dtype, m, false, true), BLOCK, 0) != hipSuccess)
     return 0;
+  nb = nb < nb2 ? nb : nb2;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   return nb * ncu;
 }
@@ -2585,7 +2881,7 @@ int max_coresident(int kind, int dtype, int m, int device) {
 hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative) {
   Desc copy = d;
   void* args[] = {&copy};
-  const void* fn = kernel_fn(d.kind, d.dtype, d.m, d.eq_mask != 0);
+  const void* fn = kernel_fn(d.kind, d.dtype, d.m, d.eq_mask != 0, d.compact && d.cbuf);
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
   return hipLaunchKernel(fn, dim3(grid), dim3(BLOCK), args, 0, stream);
 }

@@ -39,7 +39,7 @@ def test_struct_layouts_match_binding():
     L = N.lib()
     for i, S in enumerate(N.STRUCTS):
         assert L.pgdto_struct_size(i) == ctypes.sizeof(S), S.__name__
-    assert L.pgdto_version() == 6
+    assert L.pgdto_version() == 7
     assert N.status_string(N.ERR_ARG) == "invalid argument"
 
 
