@@ -57,10 +57,11 @@
 extern "C" {
 #endif
 
-#define PGDTO_VERSION 7      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
+#define PGDTO_VERSION 8      /* 2: eq_mask, automatic C, pgdto_result.kappa; 3: lambda0, 5 tune shapes;
                                 4: pgdto_result.lambda_err, x_err; 5: pgdto_project_noalloc;
                                 6: pgdto_project_batch_async, pgdto_pgd_step_batch_async;
-                                7: pgdto_params.compact, pgdto_pgd_args.work, autotune save/load */
+                                7: pgdto_params.compact, pgdto_pgd_args.work, autotune save/load;
+                                8: pgdto_result.dist2, pgdto_kappa_path */
 #define PGDTO_MAX_M 8        /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
@@ -224,6 +225,8 @@ typedef struct {
   int32_t passes_compacted;  /* search passes that streamed only the kept
                             elements (max over rows / blocks)                */
   int32_t reserved;
+  double dist2;          /* ||x - y||_2^2 of x as stored: the distance the
+                            projection moved the point (y = rho~ for a step) */
 } pgdto_result;
 
 typedef struct {
@@ -341,6 +344,31 @@ int pgdto_project_async(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_p
 #define PGDTO_NOALLOC_SCRATCH_BYTES 1466752
 int pgdto_project_noalloc(const pgdto_problem* prob, const pgdto_params* params, pgdto_result* result_dev,
                           void* stream);
+
+/* kappa-continuation (Appendix A.2, the closing remark on choosing C: for
+ * an infeasible subproblem C trades constraint violation against the
+ * distance the projection moves the point).  Solves prob at each penalty
+ * C_values[0..count-1] (count 1..64; each > 0 or INFINITY, or < 0 for the
+ * automatic choice with tolerance -C), in that order, each solve
+ * warm-started from the previous point's multipliers (the first from
+ * prob->lambda0 when given), and fills points[i] (host memory).  prob->x
+ * holds the last point's x on return.  tau > 0 also states each point's
+ * worst violation against that tolerance (0: not stated).  Blocking; one
+ * launch per point.  PGDTO_ERR_ARG for an invalid problem or list. */
+typedef struct {
+  double C, kappa;                         /* penalty asked for and kappa used     */
+  double dist;                             /* ||x - y||_2 of x as stored           */
+  double max_violation;                    /* max_j violation[j]                   */
+  double violation_over_tau;               /* max_violation / tau (0 if tau = 0)   */
+  int32_t outcome, passes;
+  double lambda[PGDTO_MAX_BLOCKS];         /* multipliers                          */
+  double slack[PGDTO_MAX_BLOCKS];          /* kappa lambda_j: the violation the
+                                              regularized problem allows (eq. s_y_robust) */
+  double violation[PGDTO_MAX_BLOCKS];      /* max(0, a_j.x - b_j) (equality rows:
+                                              |a_j.x - b_j|) of x as stored        */
+} pgdto_path_point;
+int pgdto_kappa_path(pgdto_ctx* ctx, const pgdto_problem* prob, const pgdto_params* params, const double* C_values,
+                     int count, double tau, pgdto_path_point* points, void* stream);
 
 /* One body of Algorithm 3 (step size, direction, rho~, projection, stop test),
  * one launch; waits and fills *out.  The _async form writes the
@@ -476,7 +504,8 @@ int pgdto_trace_read(pgdto_ctx* ctx, uint64_t* out, int max_records);
 
 /* Layout introspection for language bindings: sizeof of the public structs.
  * which: 0 pgdto_problem, 1 pgdto_params, 2 pgdto_result, 3 pgdto_pgd_args,
- * 4 pgdto_pgd_out, 5 pgdto_batch_cfg.  Returns 0 for an unknown index. */
+ * 4 pgdto_pgd_out, 5 pgdto_batch_cfg, 6 pgdto_path_point.  Returns 0 for an
+ * unknown index. */
 size_t pgdto_struct_size(int which);
 
 #ifdef __cplusplus

@@ -16,6 +16,8 @@ Contents
   projection.brute_force      enumeration of element states and active rows
   projection.auto_C           the penalty bounding constraint violation by tau
                               (Appendix A.2), from the largest breakpoint
+  projection.kappa_path       the projection along a list of penalties C
+                              (Appendix A.2: violation against distance)
   literal.alg1_bisection      Algorithm 1 as printed (float64), for iteration counts
   literal.alg2_newton         Algorithm 2 (Stage 1 + semismooth Newton), float64
   pgd.pgd_step                one step of Algorithm 3 around the projection
@@ -26,10 +28,10 @@ quantities left unpinned are the literal algorithms' iteration counts
 """
 from .projection import (clip_map, h_map, exact_single, project, coupled,
                          kkt_certificate, brute_force, row_scale, OracleResult,
-                         largest_breakpoint, auto_C)
+                         largest_breakpoint, auto_C, kappa_path)
 from .pgd import pgd_step, step_size, cg_beta, PgdParams
 from . import literal
 
 __all__ = ["clip_map", "h_map", "exact_single", "project", "coupled", "kkt_certificate",
-           "brute_force", "row_scale", "OracleResult", "largest_breakpoint", "auto_C", "pgd_step", "step_size", "cg_beta",
+           "brute_force", "row_scale", "OracleResult", "largest_breakpoint", "auto_C", "kappa_path", "pgd_step", "step_size", "cg_beta",
            "PgdParams", "literal"]

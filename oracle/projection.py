@@ -431,3 +431,31 @@ def project(kind, y, A, b, lo, hi, C=math.inf, offsets=None, eq=None):
         resid = np.array([fsum(Ad[j] * x) - b[j] for j in range(m)])
     n_free = int(np.count_nonzero((z >= lo) & (z <= hi)))
     return OracleResult(x, z, lam, outcome, resid, kappa * lam, n_free, kappa)
+
+
+def kappa_path(kind, y, A, b, lo, hi, C_values, offsets=None, eq=None, tau=0.0):
+    """The regularized projection along a list of penalties (Appendix A.2,
+    the remark that closes the choice of C: for an infeasible subproblem, C
+    trades the violation of the constraints against the distance the
+    projection moves the point).  Every point is its own solve: the
+    projection is unique for each kappa > 0, so no continuation is needed to
+    define it.  A negative C asks for the automatic penalty with tau = -C.
+
+    Per point: kappa, the multipliers, the slack kappa lam_j, the violation
+    max(0, a_j.x - b_j) of every row (|a_j.x - b_j| for an equality row), its
+    largest entry and 2-norm, the distance ||x - y||_2, and the largest
+    violation over tau when tau > 0."""
+    y = np.asarray(y, dtype=np.float64)
+    m = np.asarray(b, dtype=np.float64).size
+    eqa = np.zeros(m, dtype=bool) if eq is None else np.asarray(eq, dtype=bool).reshape(-1)
+    pts = []
+    for Cv in C_values:
+        C_eff = auto_C(kind, y, A, lo, hi, -Cv, offsets) if Cv < 0 else Cv
+        r = project(kind, y, A, b, lo, hi, C_eff, offsets, eq=eq)
+        viol = np.where(eqa, np.abs(r.resid), np.maximum(r.resid, 0.0))
+        dist = math.sqrt(fsum((r.x - y) ** 2))
+        vmax = float(np.max(viol)) if viol.size else 0.0
+        pts.append({"C": Cv, "kappa": r.kappa, "lam": r.lam.copy(), "slack": r.slack.copy(), "violation": viol,
+                    "max_violation": vmax, "violation_norm": math.sqrt(fsum(viol ** 2)), "dist": dist,
+                    "violation_over_tau": vmax / tau if tau > 0 else 0.0, "result": r})
+    return pts

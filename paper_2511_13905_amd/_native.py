@@ -58,7 +58,7 @@ class Result(C.Structure):
                 ("slack", C.c_double * MAX_BLOCKS), ("row_outcome", C.c_int32 * MAX_BLOCKS),
                 ("res_inf", C.c_double), ("lambda_width", C.c_double), ("kappa", C.c_double),
                 ("lambda_err", C.c_double * MAX_BLOCKS), ("x_err", C.c_double), ("n_compact", C.c_int64),
-                ("passes_compacted", C.c_int32), ("reserved", C.c_int32)]
+                ("passes_compacted", C.c_int32), ("reserved", C.c_int32), ("dist2", C.c_double)]
 
     def to_dict(self) -> dict:
         m = self.m
@@ -71,7 +71,7 @@ class Result(C.Structure):
                 "row_outcome": [OUTCOME_NAMES.get(o, str(o)) for o in self.row_outcome[:m]],
                 "res_inf": self.res_inf, "lambda_width": self.lambda_width, "kappa": self.kappa,
                 "lambda_err": list(self.lambda_err[:m]), "x_err": self.x_err, "n_compact": self.n_compact,
-                "passes_compacted": self.passes_compacted}
+                "passes_compacted": self.passes_compacted, "dist2": self.dist2}
 
 
 class PgdArgs(C.Structure):
@@ -99,7 +99,20 @@ class BatchCfg(C.Structure):
                 ("wg_per_slot", C.c_int32), ("queue_capacity", C.c_int32), ("slots_only", C.c_int32)]
 
 
-STRUCTS = [Problem, Params, Result, PgdArgs, PgdOut, BatchCfg]
+class PathPoint(C.Structure):
+    _fields_ = [("C", C.c_double), ("kappa", C.c_double), ("dist", C.c_double), ("max_violation", C.c_double),
+                ("violation_over_tau", C.c_double), ("outcome", C.c_int32), ("passes", C.c_int32),
+                ("lambda_", C.c_double * MAX_BLOCKS), ("slack", C.c_double * MAX_BLOCKS),
+                ("violation", C.c_double * MAX_BLOCKS)]
+
+    def to_dict(self, m: int) -> dict:
+        return {"C": self.C, "kappa": self.kappa, "dist": self.dist, "max_violation": self.max_violation,
+                "violation_over_tau": self.violation_over_tau,
+                "outcome": OUTCOME_NAMES.get(self.outcome, str(self.outcome)), "passes": self.passes,
+                "lam": list(self.lambda_[:m]), "slack": list(self.slack[:m]), "violation": list(self.violation[:m])}
+
+
+STRUCTS = [Problem, Params, Result, PgdArgs, PgdOut, BatchCfg, PathPoint]
 
 # every function the header declares: name -> (restype, argtypes)
 _VP = C.c_void_p
@@ -137,6 +150,8 @@ SIGNATURES = {
     "pgdto_problem_check": (C.c_int, [C.POINTER(Problem), C.POINTER(Params)]),
     "pgdto_struct_size": (C.c_size_t, [C.c_int]),
     "pgdto_trace_read": (C.c_int, [_VP, C.POINTER(C.c_uint64), C.c_int]),
+    "pgdto_kappa_path": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_double), C.c_int,
+                                   C.c_double, C.POINTER(PathPoint), _VP]),
 }
 
 _lib = None

@@ -229,6 +229,21 @@ class Context:
         _check(st, "pgdto_project_async")
         return x
 
+    def kappa_path(self, kind, y, A, b, lo, hi, C_values, tau=0.0, offsets=None, x=None, params=None, eq=None,
+                   lam0=None, stream=None):
+        """pgdto_kappa_path: the projection along a sequence of penalties C,
+        each solve warm-started from the previous multipliers; returns (x of
+        the last point, [point dicts])."""
+        keep = _Keep()
+        s, x, _A = problem_struct(kind, y, A, b, lo, hi, math.inf, offsets, x, None, keep, eq=eq, lam0=lam0)
+        p = params if isinstance(params, N.Params) else make_params(**(params or {}))
+        cs = keep.dbl(list(C_values))
+        pts = (N.PathPoint * len(C_values))()
+        st = N.lib().pgdto_kappa_path(self.h, C_byref(s), C_byref(p), cs, len(C_values), float(tau), pts,
+                                      _stream(self.device, stream))
+        _check(st, "pgdto_kappa_path")
+        return x, [pt.to_dict(s.m) for pt in pts]
+
     # ------------------------------------------------------------ Alg. 3 step
     def _pgd_struct(self, kind, A, rho, rho_prev, grad, grad_prev, d, g, G, t, lo, hi, C, offsets, x,
                     hyper, keep, copy_ok=True, eq=None, lam0=None, work=None):

@@ -69,5 +69,22 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
     return lib
 
 
+def sanitized_tests() -> int:
+    """The CPU test suite (-m "not gpu") against libpgdto_san.so, with the
+    clang AddressSanitizer runtime preloaded into python (leak checks off:
+    the interpreter itself keeps memory until exit)."""
+    env = dict(os.environ)
+    env["PGDTO_LIB"] = LIB_SAN
+    env["LD_PRELOAD"] = asan_runtime()
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+    root = os.path.dirname(HERE)
+    cmd = [sys.executable, "-m", "pytest", os.path.join(root, "tests"), "-q", "-m", "not gpu", "-p", "no:cacheprovider"]
+    return subprocess.run(cmd, env=env, cwd=root).returncode
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))
+    san = "--sanitize" in sys.argv
+    print(build(verbose="-v" in sys.argv, sanitize=san))
+    if san and "--test" in sys.argv:
+        sys.exit(sanitized_tests())

@@ -102,6 +102,7 @@ extern "C" size_t pgdto_struct_size(int which) {
     case 3: return sizeof(pgdto_pgd_args);
     case 4: return sizeof(pgdto_pgd_out);
     case 5: return sizeof(pgdto_batch_cfg);
+    case 6: return sizeof(pgdto_path_point);
     default: return 0;
   }
 }
@@ -577,4 +578,46 @@ extern "C" int pgdto_pgd_step(pgdto_ctx* c, const pgdto_pgd_args* args, const pg
   st = finish_blocking(c, (hipStream_t)stream, sizeof(pgdto_pgd_out), out);
   if (st != PGDTO_OK) return st;
   return out->proj.error ? out->proj.error : PGDTO_OK;
+}
+
+extern "C" int pgdto_kappa_path(pgdto_ctx* c, const pgdto_problem* prob, const pgdto_params* params,
+                                const double* C_values, int count, double tau, pgdto_path_point* points,
+                                void* stream) {
+  if (!c || !prob || !C_values || !points || count < 1 || count > 64 || !(tau >= 0.0) || !isfinite(tau))
+    return PGDTO_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    const double Ci = C_values[i];
+    if (isnan(Ci) || Ci == 0.0 || Ci == -INFINITY) return PGDTO_ERR_ARG;
+  }
+  pgdto_problem p = *prob;
+  double warm[PGDTO_MAX_BLOCKS];
+  for (int i = 0; i < count; ++i) {
+    p.C = C_values[i];
+    pgdto_result r;
+    int st = pgdto_project(c, &p, params, &r, stream);
+    if (st != PGDTO_OK) return st;
+    pgdto_path_point& pt = points[i];
+    memset(&pt, 0, sizeof(pt));
+    pt.C = C_values[i];
+    pt.kappa = r.kappa;
+    pt.dist = sqrt(fmax(r.dist2, 0.0));
+    pt.outcome = r.outcome;
+    pt.passes = r.passes;
+    double vmax = 0.0;
+    bool warm_ok = true;
+    for (int j = 0; j < p.m; ++j) {
+      const bool eq = (p.eq_mask >> j) & 1ull;
+      pt.lambda[j] = r.lambda[j];
+      pt.slack[j] = r.slack[j];
+      pt.violation[j] = eq ? fabs(r.resid[j]) : fmax(r.resid[j], 0.0);
+      vmax = fmax(vmax, pt.violation[j]);
+      warm[j] = r.lambda[j];
+      warm_ok = warm_ok && isfinite(r.lambda[j]) && (eq || r.lambda[j] >= 0.0);
+    }
+    pt.max_violation = vmax;
+    pt.violation_over_tau = tau > 0.0 ? vmax / tau : 0.0;
+    // the next point starts from these multipliers (continuation)
+    p.lambda0 = warm_ok ? warm : nullptr;
+  }
+  return PGDTO_OK;
 }

@@ -819,6 +819,7 @@ __device__ __forceinline__ void pgd_scalars(const Desc& d, const double* v, PgdS
 constexpr int META_ROWS = 3 * NWAVE;
 constexpr int META_ROW = VMAX - META_ROWS;
 constexpr int NV_SEARCH = 2 * NT + 1;      // per trial a.x and slope, then the pairs kept
+constexpr int NV_FINAL1 = 5;               // a.x, free count, |x - rho|^2, |x|^2 (pgd), |x - y|^2
 
 __device__ __forceinline__ double* meta_row(const Desc& d, int r) {
   return d.part + (size_t)(META_ROW + r) * TILES_PAD;      // buffer 0
@@ -1350,8 +1351,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
                                        cs[0][1] + cs[1][1], (double)sl[0][1] + (double)sl[1][1], kept};
         block_to_part<NV_SEARCH>(acc, nv, maxmask, sh.red, pb, tile);
       } else {  // PH_FINAL
-        nv = 4; maxmask = 0;
-        double acc[4] = {0, 0, 0, 0};
+        nv = NV_FINAL1; maxmask = 0;
+        double acc[NV_FINAL1] = {0, 0, 0, 0, 0};
         const double lam = (EQ ? sh.sg[s] : 1.0) * sh.S.lam[s];
         const T* R = (const T*)d.rho;
         // x = clip(y - lam a) in the stream precision; a.x, free count, pgd norms
@@ -1371,6 +1372,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               acc[2] = fma(df, df, acc[2]);
               acc[3] = fma(xr, xr, acc[3]);
             }
+            const double dy = xr - f64(yv[q]);            // distance of the projection
+            acc[4] = fma(dy, dy, acc[4]);
           }
           st_vec<T>(X, e0, mask, full, xo);
           return bits;
@@ -1443,7 +1446,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             if (d.free_mask) put_mask(any, e0, bits, g);
           }
         }
-        block_to_part<4>(acc, nv, maxmask, sh.red, pb, tile);
+        block_to_part<NV_FINAL1>(acc, nv, maxmask, sh.red, pb, tile);
       }
     }
     if (ph == PH_SEARCH && CB != nullptr) {
@@ -1527,7 +1530,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
     }
     if (ph == PH_ZERO) { nv = EQ ? 9 : 7; maxmask = (EQ ? ((1ull << 2) | (1ull << 6)) : (1ull << 2)) | (1ull << (nv - 1)); }
     else if (ph == PH_SEARCH) { nv = NV_SEARCH; maxmask = 0; }
-    else { nv = 4; maxmask = 0; }
+    else { nv = NV_FINAL1; maxmask = 0; }
 
     trace_put(d, pass_no, 1, clk());
     trace_wg(d, pass_no, t_pass0, clk());
@@ -1599,7 +1602,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         pgdto_result* R = d.pgd ? &((pgdto_pgd_out*)d.result)->proj : (pgdto_result*)d.result;
         for (int s = tid; s < d.nseg; s += BLOCK) {
           const double lam_s = (EQ ? sh.sg[s] : 1.0) * sh.S.lam[s];
-          const double r = sh.tot[s * 4 + 0] - sh.bs[s];
+          const double r = sh.tot[s * NV_FINAL1 + 0] - sh.bs[s];
           R->lambda[s] = lam_s;
           R->resid[s] = r;
           R->slack[s] = kappa * lam_s;
@@ -1615,7 +1618,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         __syncthreads();
         if (tid == 0) {
           int worst = PGDTO_INACTIVE, anyact = 0, np = 0;
-          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0, rmax = 0.0, xerr = 0.0, ncomp = -1.0;
+          double nfree = 0.0, diff2 = 0.0, xx = 0.0, wmax = 0.0, rmax = 0.0, xerr = 0.0, ncomp = -1.0, dist2 = 0.0;
           int npc = 0;
           for (int s = 0; s < d.nseg; ++s) {
             if (severity(sh.S.outcome[s]) > severity(worst)) worst = sh.S.outcome[s];
@@ -1625,14 +1628,16 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             rmax = fmax(rmax, sh.red[s]);
             // blocks are disjoint: the element error is the largest block's
             xerr = fmax(xerr, sh.amax[s] * sh.red[PGDTO_MAX_BLOCKS + s]);
-            nfree += sh.tot[s * 4 + 1];
-            diff2 += sh.tot[s * 4 + 2];
-            xx += sh.tot[s * 4 + 3];
+            nfree += sh.tot[s * NV_FINAL1 + 1];
+            diff2 += sh.tot[s * NV_FINAL1 + 2];
+            xx += sh.tot[s * NV_FINAL1 + 3];
+            dist2 += sh.tot[s * NV_FINAL1 + 4];
             if (sh.ncomp[s] >= 0.0) ncomp = fmax(ncomp, 0.0) + sh.ncomp[s];
             npc = max(npc, sh.npc[s]);
           }
           R->n_compact = (int64_t)ncomp;
           R->passes_compacted = npc;
+          R->dist2 = dist2;
           R->outcome = worst;
           R->error = 0;
           R->path = anyact ? 1 : 0;
@@ -1785,7 +1790,7 @@ template <int M> struct CN {
   static constexpr int NV_S1 = 2 * NT * M;
   static constexpr int NV_NEWTON = M + NJ;
   static constexpr int NV_CHECK = M * M + (FUSE ? NV_NEWTON : 0);
-  static constexpr int NV_FINAL = M + 3;
+  static constexpr int NV_FINAL = M + 4;         // a.x per row, free count, pgd norms, |x - y|^2
   static constexpr int U = (M <= 2) ? 4 : 2;     // vector slots in flight per chunk
   static constexpr int NVM = NV_CHECK > NV_ZERO ? (NV_CHECK > NV_S1 ? NV_CHECK : NV_S1) : (NV_ZERO > NV_S1 ? NV_ZERO : NV_S1);
 };
@@ -2372,6 +2377,8 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
                 acc[M + 1] = fma(df, df, acc[M + 1]);
                 acc[M + 2] = fma(xr, xr, acc[M + 2]);
               }
+              const double dy = xr - f64(yv[q]);          // distance of the projection
+              acc[M + 3] = fma(dy, dy, acc[M + 3]);
             }
             st_vec<T>(X, e0, mask, full, xo);
           }
@@ -2581,6 +2588,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
           R->res_inf = rmax;
           R->n_compact = -1;                       // the coupled path does not compact
           R->passes_compacted = 0;
+          R->dist2 = t[M + 3];
           R->x_err = xerr + half_ulp(fmax(fabs(lo), fabs(hi)), sizeof(T) == 4);
           double wmax = 0.0;
           for (int j = 0; j < M; ++j) wmax = fmax(wmax, sh.S.width[j]);

@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pgdto.h")
-LIB = os.path.join(ROOT, "paper_2511_13905_amd", "libpgdto.so")
+LIB = os.environ.get("PGDTO_LIB") or os.path.join(ROOT, "paper_2511_13905_amd", "libpgdto.so")
 
 
 def declared_functions():
@@ -39,7 +39,7 @@ def test_struct_layouts_match_binding():
     L = N.lib()
     for i, S in enumerate(N.STRUCTS):
         assert L.pgdto_struct_size(i) == ctypes.sizeof(S), S.__name__
-    assert L.pgdto_version() == 7
+    assert L.pgdto_version() == 8
     assert N.status_string(N.ERR_ARG) == "invalid argument"
 
 

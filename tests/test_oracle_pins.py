@@ -408,3 +408,53 @@ def test_generators_shape_and_recipe():
     q = I.volume_com(1, grid=(24, 12, 12))
     assert not q.meta["feasible"]
     assert q.A.shape == (5, 24 * 12 * 12) and q.A.dtype == np.float32
+
+
+# ---------------------------------------------------------------- kappa path (Appendix A.2, choosing C)
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_kappa_path_trades_violation_for_distance(seed, m):
+    """Along increasing C (a heavier penalty 1/kappa on the slack), the
+    penalized problem min 1/2|x - y|^2 + 1/(2 kappa) |(Ax - b)_+|^2 can only
+    lower the violation norm and raise the distance (the monotonicity of a
+    quadratic penalty method); each point equals the enumerated solution of
+    its own kappa (brute force), so the path is pinned point by point."""
+    rng = np.random.default_rng(500 + 10 * seed + m)
+    n = 6 if m < 3 else 5
+    y, A, b = _random_case(rng, n, m, "infeasible")
+    kind = "coupled" if m > 1 else "single"
+    Cs = [2.0, 20.0, 200.0, 2e3, 2e4]
+    pts = oracle.kappa_path(kind, y, A, b, 0.0, 1.0, Cs)
+    for p in pts:
+        sv = P.brute_force(y, A, b, 0.0, 1.0, p["kappa"])
+        np.testing.assert_allclose(p["result"].x, sv[0], atol=1e-8)
+        assert p["dist"] == pytest.approx(math.sqrt(P.fsum((sv[0] - y) ** 2)), abs=1e-7)
+    for p, q in zip(pts, pts[1:]):
+        assert q["violation_norm"] <= p["violation_norm"] + 1e-9
+        assert q["dist"] >= p["dist"] - 1e-9
+    # the infeasible row stays violated; the slack kappa lam_j is the
+    # violation the regularized optimum keeps: kappa lam_j = (a_j.x - b_j)_+
+    for p in pts:
+        np.testing.assert_allclose(p["slack"], p["violation"], atol=1e-7)
+
+
+def test_kappa_path_single_row_closed_form():
+    """One infeasible row: every point is the saturated x with
+    lam = (a.x_sat - b)/kappa, so the violation is constant and the distance
+    too (hand-checkable; the slack equals the violation at every C)."""
+    rng = np.random.default_rng(23)
+    n = 300
+    y = rng.uniform(-0.5, 1.5, n)
+    a = rng.uniform(0.1, 1.0, n)
+    lo, hi = 0.1, 1.0
+    x_sat = np.full(n, lo)
+    gap = 3.0
+    b = P.fsum(a * x_sat) - gap
+    pts = oracle.kappa_path("single", y, a.reshape(1, n), [b], lo, hi, [1e2, 1e4, 1e6], tau=0.5)
+    d_sat = math.sqrt(P.fsum((x_sat - y) ** 2))
+    for p in pts:
+        assert p["lam"][0] == pytest.approx(gap / p["kappa"], rel=1e-12)
+        assert p["max_violation"] == pytest.approx(gap, rel=1e-12)
+        assert p["violation_over_tau"] == pytest.approx(gap / 0.5, rel=1e-12)
+        assert p["dist"] == pytest.approx(d_sat, rel=1e-12)
