@@ -63,7 +63,11 @@ def parse():
 # scaled by the same counters on a plain 1 GiB copy.  Reported only while the
 # kernel source is the one that was measured (sha256 of the HIP file).
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # profiles/k_batch_f32_pgd_compliance_b16_hbm_traffic.md
+    "pgd_compliance": {"kernel_sha": "eaed232f37009b9a", "bytes_per_launch": 6547169749,
+                       "read": 5644820912, "written": 902348836, "instances": 16},
+}
 
 
 def kernel_sha():
@@ -72,9 +76,9 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_for(workload):
+def traffic_for(workload, instances):
     m = MEASURED_TRAFFIC.get(workload)
-    if not m or m["kernel_sha"] != kernel_sha():
+    if not m or m["kernel_sha"] != kernel_sha() or m["instances"] != instances:
         return None
     return m
 
@@ -292,7 +296,7 @@ def main():
         compulsory = sum(st.n * ESZ * (rows + 2) for st in states)
     elems = B * n if is_pgd else sum(st.n for st in states)
     achieved = bytes_launch / (kern_ms * 1e-3)
-    tr = traffic_for(wl)
+    tr = traffic_for(wl, B)
     line = {
         "metric": "projected elements/s and % HBM roofline; p50/p99 batched projection latency",
         "value": elems / (ms_step * 1e-3),
