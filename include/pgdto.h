@@ -25,7 +25,18 @@
  *                      in one launch.
  *   PGDTO_COUPLED      m <= PGDTO_MAX_M dense rows: Algorithm 2 (Stage 1
  *                      single-active searches, then semismooth Newton with a
- *                      line search, Appendix A.2).
+ *                      line search, Appendix A.2).  Up to 8 rows every
+ *                      route and dtype; 9 to 64 rows (the Jacobian sums
+ *                      A D A^T of eq. reg_jacobian on the matrix cores, the
+ *                      Stage-1 candidate check in float64 on the matrix
+ *                      cores, a workgroup-parallel float64 LDL^T of the
+ *                      active block): float32 projections through
+ *                      pgdto_project / pgdto_project_async only; other
+ *                      routes (Algorithm 3 steps, batches, serving,
+ *                      pgdto_project_noalloc) return PGDTO_ERR_ARG
+ *                      (pgdto_project_noalloc: PGDTO_ERR_SCRATCH).  The
+ *                      context allocates a 4.6 MiB workspace for it at
+ *                      its first such call.
  *
  * pgdto_pgd_step additionally performs one iteration body of Algorithm 3:
  * step size (eq. final_alpha with the fallback rule), conjugate direction
@@ -62,7 +73,7 @@ extern "C" {
                                 6: pgdto_project_batch_async, pgdto_pgd_step_batch_async;
                                 7: pgdto_params.compact, pgdto_pgd_args.work, autotune save/load;
                                 8: pgdto_result.dist2, pgdto_kappa_path */
-#define PGDTO_MAX_M 8        /* coupled rows */
+#define PGDTO_MAX_M 64       /* coupled rows */
 #define PGDTO_MAX_BLOCKS 64  /* independent blocks */
 
 typedef enum {

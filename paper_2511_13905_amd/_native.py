@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # libpgdto_san.so, for the CPU test suite)
 LIB_PATH = os.environ.get("PGDTO_LIB") or os.path.join(HERE, "libpgdto.so")
 
-MAX_M = 8
+MAX_M = 64          # coupled rows (beyond SMALL_M: float32 projections, one-instance launches)
+SMALL_M = 8
 MAX_BLOCKS = 64
 
 # enums (pgdto.h)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpgdto.so")
 
-SOURCES = ["pgdto_kernels.hip", "pgdto_host.cpp", "pgdto_serve.cpp", "pgdto_server.cpp", "pgdto_many.cpp"]
+SOURCES = ["pgdto_kernels.hip", "pgdto_wide.hip", "pgdto_host.cpp", "pgdto_serve.cpp", "pgdto_server.cpp", "pgdto_many.cpp"]
 
 # Packed-FP32 instructions are disabled: hipcc -O3 forms them from float2
 # code and some forms have given wrong results on these machines.

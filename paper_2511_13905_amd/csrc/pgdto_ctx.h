@@ -33,6 +33,8 @@ struct pgdto_ctx {
   hipEvent_t bt_ev[pgdto::BATCH_RING] = {};
   int bt_next = 0;
   uint64_t bt_seq = 0;
+  // workspace of the wide coupled kernel (m > SMALL_M), allocated at first use
+  double* wide = nullptr;
 };
 
 namespace pgdto {
@@ -40,4 +42,6 @@ int validate_params(const pgdto_params* p);
 int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Desc& d);
 int fill_pgd(const pgdto_pgd_args* a, Desc& d);
 int grid_for(pgdto_ctx* c, const Desc& d);
+// a coupled problem beyond SMALL_M rows (the wide kernel; one-instance projections only)
+inline bool is_wide(const Desc& d) { return d.kind == PGDTO_COUPLED && d.m > SMALL_M; }
 }  // namespace pgdto

@@ -160,6 +160,7 @@ extern "C" int pgdto_ctx_destroy(pgdto_ctx* c) {
   if (c->res_dev) (void)hipFree(c->res_dev);
   if (c->res_host) (void)hipHostFree(c->res_host);
   if (c->trace) (void)hipFree(c->trace);
+  if (c->wide) (void)hipFree(c->wide);
   if (c->bt_part) (void)hipFree(c->bt_part);
   if (c->bt_sync) (void)hipFree(c->bt_sync);
   for (int r = 0; r < BATCH_RING; ++r) {
@@ -203,7 +204,11 @@ int build_desc(const pgdto_problem* pr, const pgdto_params* pp, bool need_y, Des
   switch (pr->kind) {
     case PGDTO_SINGLE: if (pr->m != 1) return PGDTO_ERR_ARG; break;
     case PGDTO_INDEPENDENT: if (pr->m < 1 || pr->m > PGDTO_MAX_BLOCKS) return PGDTO_ERR_ARG; break;
-    case PGDTO_COUPLED: if (pr->m < 1 || pr->m > PGDTO_MAX_M) return PGDTO_ERR_ARG; break;
+    case PGDTO_COUPLED:
+      if (pr->m < 1 || pr->m > PGDTO_MAX_M) return PGDTO_ERR_ARG;
+      // beyond SMALL_M rows: float32 projections (the wide kernel)
+      if (pr->m > SMALL_M && (pr->dtype != PGDTO_F32 || !need_y)) return PGDTO_ERR_ARG;
+      break;
     default: return PGDTO_ERR_ARG;
   }
   if ((need_y && !pr->y) || !pr->A || !pr->x || !pr->b) return PGDTO_ERR_ARG;
@@ -319,9 +324,29 @@ int grid_for(pgdto_ctx* c, const Desc& d) {
   return it != c->tuned_grid.end() ? std::min(it->second, full) : full;
 }
 
+// The wide kernel's workspace, allocated and cleared at the first wide
+// launch of the context (its flags must start below every epoch).
+static double* wide_workspace(pgdto_ctx* c) {
+  if (c->wide) return c->wide;
+  double* w = nullptr;
+  if (hipMalloc(&w, WIDE_WORDS * sizeof(double)) != hipSuccess) return nullptr;
+  if (hipMemset(w, 0, WIDE_WORDS * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(w);
+    return nullptr;
+  }
+  c->wide = w;
+  return w;
+}
+
 int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_pgd) {
   d.part = c->part;
   d.sync = c->sync;
+  d.wide = nullptr;
+  if (is_wide(d)) {
+    if (is_pgd || d.ntiles > WTILES) return PGDTO_ERR_ARG;
+    d.wide = wide_workspace(c);
+    if (!d.wide) return PGDTO_ERR_NOMEM;
+  }
   c->launch_seq += 1;
   d.epoch0 = c->launch_seq << 20;   // replaced on the device by the door's generation
   d.trace = c->trace;

@@ -14,7 +14,8 @@ constexpr int NT = 2;                      // trial multipliers per 1-D search p
 constexpr int TARGET_TILES = 512;          // bound the partial-sum layout is sized for (instances use half)
 constexpr int MAX_TILES = TARGET_TILES + PGDTO_MAX_BLOCKS + 8;
 constexpr int TILES_PAD = 704;             // stride of the partial-sum table
-constexpr int VMAX = 112;                  // partial values per tile (coupled, m = 8)
+constexpr int SMALL_M = 8;                 // coupled rows of the register-accumulating kernel
+constexpr int VMAX = 112;                  // partial values per tile (coupled, m = SMALL_M)
 constexpr int PART_DOUBLES = 2 * VMAX * TILES_PAD;   // double-buffered
 constexpr int GMAX = 1024;                 // workgroups of one launch (upper bound)
 constexpr int TOT_MAX = 1024;              // per-segment totals of one pass
@@ -69,6 +70,7 @@ struct Desc {
   // workspace
   double* part;          // [2][VMAX][TILES_PAD]
   uint64_t* sync;        // epoch flags, go word, error word, totals
+  double* wide;          // workspace of the wide coupled kernel (m > SMALL_M), else NULL
   uint64_t epoch0;       // epoch base (pass p publishes epoch0 + p + 1): from the arrival
                          // door's generation in one-instance launches, per job in the server
   void* result;          // pgdto_result (pgd: pgdto_pgd_out)
@@ -139,6 +141,26 @@ struct BatchArgs {
 constexpr int BATCH_MAX = 256;          // instances per batch launch
 constexpr int BATCH_RING = 4;           // pinned descriptor areas per context (reused in turn)
 constexpr int BATCH_JOB_SHIFT = 16;     // passes per job stay below 2^16
+
+// ------------------------------------------------------------------ wide coupled kernel
+// m in (SMALL_M, PGDTO_MAX_M] dense rows: the Newton sums are reduced through
+// a table of WV values per tile, in a workspace of its own (per context).
+constexpr int WM = PGDTO_MAX_M;                 // rows
+constexpr int WNJ = WM * (WM + 1) / 2;          // Jacobian sums (upper triangle)
+constexpr int WCAND = 16;                       // Stage-1 candidates per check pass
+constexpr int WV_PAD = 2176;                    // values per tile row (>= WM + WNJ, >= WCAND * WM)
+constexpr int WTILES = TARGET_TILES / 2;        // tiles of one instance (one segment)
+constexpr int WREP = 256;                       // words per go/command replica
+static_assert(WV_PAD >= WM + WNJ && WV_PAD >= WCAND * WM, "tile row holds every pass's values");
+// workspace layout (8-byte words): per-tile partials, totals, best-trial J,
+// barrier flags (one line each), command replicas
+constexpr size_t WIDE_PART = 0;
+constexpr size_t WIDE_TOT = WIDE_PART + (size_t)WTILES * WV_PAD;
+constexpr size_t WIDE_BEST = WIDE_TOT + WV_PAD;
+constexpr size_t WIDE_FLAGS = WIDE_BEST + WV_PAD;
+constexpr size_t WIDE_REP = WIDE_FLAGS + (size_t)GMAX * 16;
+constexpr size_t WIDE_WORDS = WIDE_REP + (size_t)NREP * WREP;
+const void* wide_fn(int m);            // the kernel for m rows
 
 hipError_t launch_solve(const Desc& d, int grid, hipStream_t stream, bool cooperative);
 int max_coresident(int kind, int dtype, int m, int device);

@@ -109,7 +109,7 @@ extern "C" int pgdto_project_batch_async(pgdto_ctx* c, const pgdto_problem* prob
   for (int i = 0; i < count; ++i) {
     const int st = build_desc(&probs[i], params, true, descs[i]);
     if (st != PGDTO_OK) return st;
-    if (descs[i].dtype != PGDTO_F32) return PGDTO_ERR_ARG;
+    if (descs[i].dtype != PGDTO_F32 || is_wide(descs[i])) return PGDTO_ERR_ARG;
   }
   return launch_list(c, descs, count, slots, results_dev, 0, (hipStream_t)stream);
 }

@@ -60,7 +60,9 @@ pgdto_pgd_args Request::pgd_args() const {
 int build_request_desc(const Request& r, Desc& d) {
   if (!r.pgd) {
     const pgdto_problem p = r.problem();
-    return build_desc(&p, &r.params, true, d);
+    const int st = build_desc(&p, &r.params, true, d);
+    // the served kernel runs the register-accumulating coupled solver only
+    return (st == PGDTO_OK && is_wide(d)) ? PGDTO_ERR_ARG : st;
   }
   const pgdto_pgd_args a = r.pgd_args();
   pgdto_problem pr = a.proj;
@@ -110,6 +112,7 @@ extern "C" int pgdto_batch_submit(pgdto_batch* b, const pgdto_problem* prob, con
   Desc d;
   int st = build_desc(prob, &pp, true, d);
   if (st != PGDTO_OK) return st;
+  if (is_wide(d)) return PGDTO_ERR_ARG;     // served instances: at most SMALL_M coupled rows
   Request r;
   r.prob = *prob;
   r.params = pp;

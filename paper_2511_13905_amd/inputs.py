@@ -201,6 +201,93 @@ def volume_com(seed: int, grid=(192, 96, 96), vf: float = 0.3, target=(0.25, 0.2
                    meta={"name": name, "seed": seed, "feasible": feasible})
 
 
+def many_rows(seed: int, m: int = 64, grid=(256, 128, 128), active=None, eq_rows=(),
+              C: float = C_DEFAULT, shift: float = 0.3, margin: float = 1e-3,
+              dtype=np.float32) -> Problem:
+    """m dense coupled rows with a planted multiplier: the large-m case of
+    Alg. 2, where the Jacobian sums A D A^T of eq. (reg_jacobian) dominate a
+    Newton pass (the remark in Sec. 4.2.1 that the Jacobian is built from the
+    free variables only).
+
+    Domain [0,1] x [0, ny/nx] x [0, nz/nx], element centroids as in
+    ``volume_com``.  Rows: 0 the volume row 1/n; 1..ceil((m-1)/2) stand-ins
+    for compliance sensitivities of separate load cases, -(|N(0,1)| + 0.01)
+    times a smooth bump around a random load point plus 0.1, over n (they
+    concentrate near their load, as dC/dx does); the rest moment rows,
+    cos(pi kx X) cos(pi ky Y) cos(pi kz Z) / n with distinct random
+    frequency triples in {0..3}^3 (sign-varying, like the centre-of-mass
+    rows).
+
+    Planting: lam*_j = s u_j, u_j ~ U(0.5, 1.5), on the rows in ``active``
+    (default every fourth row, from row 0), s chosen so that the rms of
+    A^T lam* is ``shift``; rows in ``eq_rows`` are equalities and take
+    u_j of either sign.  With x* = clip(y - A^T lam*) (from the rounded
+    arrays, in float64), b_j = a_j.x* - kappa lam*_j on active rows and
+    a_j.x* + margin sigma_j on the others, so lam* satisfies the optimality
+    conditions of Appendix A.2 and is the multiplier (unique for kappa > 0).
+    The dot products are float64 BLAS sums (n is large here); the planted
+    multiplier is exact for b up to their rounding."""
+    nx, ny = grid[0], grid[1]
+    nz = grid[2] if len(grid) > 2 else 1
+    n = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    y = _step_point(rng, n).astype(dtype)
+    h = 1.0 / nx
+    X = np.repeat((np.arange(nx) + 0.5) * h, ny * nz)
+    Y = np.tile(np.repeat((np.arange(ny) + 0.5) * h, nz), nx)
+    Z = np.tile((np.arange(nz) + 0.5) * h, nx * ny)
+    ext = np.array([1.0, ny * h, nz * h])
+    A = np.empty((m, n), dtype=dtype)
+    A[0] = 1.0 / n
+    ncomp = (m - 1 + 1) // 2
+    # moment rows take distinct frequency triples (no two rows alike)
+    triples = [(a, b_, c) for a in range(4) for b_ in range(4) for c in range(4) if (a, b_, c) != (0, 0, 0)]
+    order = rng.permutation(len(triples))
+    for j in range(1, m):
+        if j <= ncomp:
+            p = rng.uniform(0.0, 1.0, 3) * ext
+            d2 = (X - p[0]) ** 2 + (Y - p[1]) ** 2 + (Z - p[2]) ** 2
+            w = np.exp(-d2 / (2.0 * 0.15 ** 2)) + 0.1
+            A[j] = (-(np.abs(rng.standard_normal(n)) + 0.01) * w / n).astype(dtype)
+        else:
+            kx, ky, kz = triples[order[j - ncomp - 1]]
+            A[j] = (np.cos(np.pi * kx * X) * np.cos(np.pi * ky * Y / ext[1]) *
+                    np.cos(np.pi * kz * Z / ext[2]) / n).astype(dtype)
+    del X, Y, Z
+    act = np.zeros(m, dtype=bool)
+    if active is None:
+        act[::4] = True
+    else:
+        act[list(active)] = True
+    eq = np.zeros(m, dtype=bool)
+    eq[list(eq_rows)] = True
+    act |= eq
+    u = rng.uniform(0.5, 1.5, m) * np.where(eq, rng.choice([-1.0, 1.0], m), 1.0)
+    u = np.where(act, u, 0.0)
+    y64 = y.astype(np.float64)
+    dirv = np.zeros(n)
+    for j in np.flatnonzero(act):
+        dirv += u[j] * A[j].astype(np.float64)
+    scale = shift / max(float(np.sqrt(np.mean(dirv * dirv))), 1e-300)
+    lam = u * scale
+    xs = np.minimum(np.maximum(y64 - scale * dirv, LO), HI)
+    del dirv
+    kappa = 0.0 if math.isinf(C) else 2.0 / C
+    b = np.empty(m)
+    sig = np.empty(m)
+    for j in range(m):
+        aj = A[j].astype(np.float64)
+        ax = float(np.dot(aj, xs))
+        sig[j] = float(np.sum(np.abs(aj))) * max(abs(LO), abs(HI))
+        b[j] = ax - kappa * lam[j] if act[j] else ax + margin * sig[j]
+    eq_mask = 0
+    for j in np.flatnonzero(eq):
+        eq_mask |= 1 << int(j)
+    return Problem("coupled", y, A, b, C=C,
+                   meta={"name": f"many_rows_m{m}_" + "x".join(str(g) for g in grid), "seed": seed,
+                         "planted_lambda": lam, "active": act, "eq_mask": eq_mask})
+
+
 @dataclass
 class PgdState:
     """Caller-owned PGD state for one step of Alg. 3 (arrays in the stream dtype)."""

@@ -88,7 +88,12 @@ def test_host_validation_without_a_device():
     assert chk(kind="coupled", m=3, lda=1000) == N.OK
     assert chk(kind="coupled", m=3, lda=1001) == N.ERR_ARG            # rows not 16-byte aligned
     assert chk(kind="coupled", m=3, lda=999) == N.ERR_ARG             # lda < n
-    assert chk(kind="coupled", m=9, lda=1000) == N.ERR_ARG            # m > PGDTO_MAX_M
+    assert chk(kind="coupled", m=9, lda=1000) == N.OK                 # the wide coupled kernel
+    assert chk(kind="coupled", m=64, lda=1000, b=[0.5] * 64) == N.OK
+    assert chk(kind="coupled", m=65, lda=1000, b=[0.5] * 65) == N.ERR_ARG   # m > PGDTO_MAX_M
+    assert chk(kind="coupled", m=9, lda=1000, dtype=N.F64) == N.ERR_ARG     # beyond 8 rows: float32 only
+    assert chk(kind="coupled", m=8, lda=1000, dtype=N.F64) == N.OK
+    assert chk(kind="coupled", m=64, lda=1000, b=[0.5] * 64, eq=1 << 63) == N.OK
     assert chk(kind="single", m=2) == N.ERR_ARG
     assert chk(n=0) == N.ERR_ARG
     assert chk(y=0x100004) == N.ERR_ARG                               # misaligned y

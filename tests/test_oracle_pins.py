@@ -458,3 +458,54 @@ def test_kappa_path_single_row_closed_form():
         assert p["max_violation"] == pytest.approx(gap, rel=1e-12)
         assert p["violation_over_tau"] == pytest.approx(gap / 0.5, rel=1e-12)
         assert p["dist"] == pytest.approx(d_sat, rel=1e-12)
+
+
+# ---------------------------------------------------------------- many coupled rows (Alg. 2 at m = 32, 64)
+
+@pytest.mark.parametrize("m,seed", [(32, 0), (32, 1), (64, 2), (64, 3)])
+def test_planted_duals_recovered_many_rows(m, seed):
+    """At m = 32 and 64 the oracle recovers the generator's planted multiplier
+    (which satisfies the optimality conditions that close Appendix A.2 by
+    construction, independently of the oracle), and both pass the KKT
+    certificate.  The plant is exact for b up to the float64 rounding of its
+    BLAS dot products, amplified by the conditioning of A D A^T."""
+    p = I.many_rows(seed, m=m, grid=(24, 16, 16))
+    A = p.A.astype(np.float64)
+    lam_star = p.meta["planted_lambda"]
+    kappa = 2.0 / p.C
+    cert_star = P.kkt_certificate(p.y, A, p.b, p.lo, p.hi, kappa, lam_star)
+    assert cert_star["max"] <= 1e-13
+    r = oracle.project("coupled", p.y, p.A, p.b, p.lo, p.hi, p.C)
+    np.testing.assert_allclose(r.lam, lam_star, rtol=0, atol=1e-7 * np.max(np.abs(lam_star)))
+    cert = P.kkt_certificate(p.y, A, p.b, p.lo, p.hi, kappa, r.lam, r.x)
+    assert cert["max"] <= 1e-12
+    assert np.count_nonzero(r.lam) == np.count_nonzero(lam_star)
+
+
+def test_planted_many_rows_equalities_and_single_active():
+    """Equality rows keep multipliers of either sign (Sec. 3.2); with one
+    active row the multiplier is that row's own 1-row solution (Alg. 2's
+    Stage-1 exit), which the 1-row oracle computes independently."""
+    p = I.many_rows(7, m=32, grid=(24, 16, 16), eq_rows=(1, 8, 19))
+    eq = [bool((p.meta["eq_mask"] >> j) & 1) for j in range(p.m)]
+    r = oracle.project("coupled", p.y, p.A, p.b, p.lo, p.hi, p.C, eq=eq)
+    lam_star = p.meta["planted_lambda"]
+    assert np.any(lam_star[np.array(eq)] < 0)
+    np.testing.assert_allclose(r.lam, lam_star, rtol=0, atol=1e-7 * np.max(np.abs(lam_star)))
+    q = I.many_rows(8, m=40, grid=(24, 16, 16), active=[5])
+    r1 = oracle.project("coupled", q.y, q.A, q.b, q.lo, q.hi, q.C)
+    ls, _ = P.exact_single(q.y, q.A[5].astype(np.float64), q.b[5], q.lo, q.hi, 2.0 / q.C)
+    assert np.count_nonzero(r1.lam) == 1
+    assert r1.lam[5] == pytest.approx(ls, rel=1e-9)
+
+
+def test_planted_many_rows_catches_a_dropped_row():
+    """A plausible mistake -- one row of A^T lam dropped from the clip map --
+    breaks the certificate of the planted multiplier at m = 64."""
+    p = I.many_rows(9, m=64, grid=(24, 16, 16))
+    A = p.A.astype(np.float64)
+    lam_star = p.meta["planted_lambda"]
+    bad = lam_star.copy()
+    bad[np.flatnonzero(lam_star)[3]] = 0.0
+    cert = P.kkt_certificate(p.y, A, p.b, p.lo, p.hi, 2.0 / p.C, bad)
+    assert cert["max"] > 1e-6
