@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--compact", action="store_true", help="turn the free-set compaction on")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes that generate the inputs (1 under a profiler)")
+    ap.add_argument("--wide-m", default="32,64",
+                    help="row counts of the many-row coupled leg (wide kernel), comma separated; empty: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -61,8 +63,10 @@ def parse():
 # HBM traffic of the timed kernel, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs of this script (summaries under profiles/), per launch and
 # scaled by the same counters on a plain 1 GiB copy.  Reported only while the
-# kernel source is the one that was measured (sha256 of the HIP file).
-KERNEL_SRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc", "pgdto_kernels.hip")
+# kernel sources are the ones that were measured (sha256 over the files).
+CSRC = os.path.join(ROOT, "paper_2511_13905_amd", "csrc")
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("pgdto_internal.h", "pgdto_device.h", "pgdto_kernels.hip")]
+WIDE_SRC = [os.path.join(CSRC, f) for f in ("pgdto_internal.h", "pgdto_device.h", "pgdto_wide.hip")]
 MEASURED_TRAFFIC = {
     # profiles/k_batch_f32_pgd_compliance_b16_hbm_traffic.md
     "pgd_compliance": {"kernel_sha": "eaed232f37009b9a", "bytes_per_launch": 6547169749,
@@ -70,10 +74,13 @@ MEASURED_TRAFFIC = {
 }
 
 
-def kernel_sha():
+def kernel_sha(files=None):
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in files or KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(workload, instances):
@@ -109,13 +116,31 @@ def _gen_proj(wl_seed):
             "volcom": I.volume_com}[wl](seed)
 
 
-def generate(fn, args, workers):
-    """Seeded instances, generated in a process pool (before the GPU is touched)."""
+WIDE_SEED = 7
+
+
+def _gen_wide(m):
+    """The many-row coupled instance of the wide leg and its candidate rows
+    (violated at lam = 0), from float64 dot products of the rounded arrays."""
+    import numpy as np
+    from paper_2511_13905_amd import inputs as I
+    p = I.many_rows(WIDE_SEED, m=m)
+    x0 = np.clip(p.y.astype(np.float64), p.lo, p.hi)
+    h0 = np.array([float(np.dot(p.A[j].astype(np.float64), x0)) for j in range(m)]) - p.b
+    return p, int(np.count_nonzero(h0 > 0.0))
+
+
+def generate(fn, args, workers, side=None):
+    """Seeded instances, generated in a process pool (before the GPU is
+    touched); side(), if given, runs in this process meanwhile."""
     if workers <= 1 or len(args) <= 1:
-        return [fn(a) for a in args]
+        out = [fn(a) for a in args]
+        return out, (side() if side else None)
     import multiprocessing as mp
     with mp.get_context("fork").Pool(min(workers, len(args))) as pool:
-        return pool.map(fn, args)
+        res = pool.map_async(fn, args)
+        extra = side() if side else None
+        return res.get(), extra
 
 
 def host_cpu():
@@ -178,10 +203,12 @@ def main():
     wl = args.workload
     B = max(1, args.batch)
     t_gen = time.perf_counter()
+    wide_ms = [int(v) for v in args.wide_m.split(",") if v.strip()]
+    wide_gen = (lambda: [_gen_wide(m) for m in wide_ms]) if wide_ms else None
     if wl == "pgd_compliance":
-        states = generate(_gen_pgd, list(range(B)), workers)
+        states, wide_insts = generate(_gen_pgd, list(range(B)), workers, wide_gen)
     else:
-        states = generate(_gen_proj, [(wl, s) for s in range(B)], workers)
+        states, wide_insts = generate(_gen_proj, [(wl, s) for s in range(B)], workers, wide_gen)
     t_gen = time.perf_counter() - t_gen
 
     # the CPU oracle runs before the GPU is initialised (its process pool forks)
@@ -336,6 +363,8 @@ def main():
         line["serving"] = serve_bench(ctx, args)
         if wl == "project_compliance":
             line["server_batch"] = server_batch_bench(ctx, insts, args)
+    if wide_insts:
+        line["wide_rows"] = [wide_bench(ctx, p, ncand, args) for p, ncand in wide_insts]
     if cpu_line is not None:
         line["cpu_baseline"] = cpu_line
         line["oracle_error"] = oracle_error(ctx, wl, states, insts, refs)
@@ -344,6 +373,103 @@ def main():
     del insts, res_buf
     torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- many coupled rows
+MFMA_F32_PEAK = 157.3e12      # dense matrix-core peak, float32 (MI355X)
+MFMA_F64_PEAK = 78.6e12       # dense matrix-core peak, float64
+
+
+def wide_work(n, m, r, ncand):
+    """Algorithmic work of one wide-kernel solve.  Each Newton pass forms
+    h (m sums) and the m (m + 1) / 2 Jacobian sums of eq. reg_jacobian
+    (2 flops per element each, float32 matrix cores); each candidate-check
+    pass (Stage-1 exit test) the nc x m sums a_k.x(lam_j e_j), nc <= 16
+    candidates per pass (float64 matrix cores).  Every pass reads y and the
+    m rows; the final pass writes x."""
+    newton = r["iters_ls"]
+    checks = max(0, r["passes"] - 2 - r["iters_search"] - newton)
+    f32 = newton * n * m * (m + 1)
+    f64 = sum(2 * n * m * min(16, ncand - 16 * i) for i in range(checks))
+    nbytes = r["passes"] * n * ESZ * (m + 1) + n * ESZ
+    return f32, f64, nbytes, checks
+
+
+def wide_bench(ctx, p, ncand, args):
+    """One-instance launches of the wide coupled kernel (m dense rows,
+    256x128x128 elements): the launch time from HIP events on the launch
+    stream, and the per-pass times of one more launch on a tracing context."""
+    import torch
+    from paper_2511_13905_amd.api import Context, aligned_rows, result_from_bytes, result_nbytes
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    y = torch.from_numpy(p.y).to(dev)
+    A = aligned_rows(torch.from_numpy(p.A).to(dev))
+    x = torch.empty_like(y)
+    buf = torch.zeros(result_nbytes(), dtype=torch.uint8, device=dev)
+
+    def launch(c):
+        c.project_async("coupled", y, A, p.b, p.lo, p.hi, buf, C=p.C, x=x)
+
+    for _ in range(2):
+        launch(ctx)
+    torch.cuda.synchronize()
+    K = max(4, min(args.steps, 10))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for i in range(K):
+        evs[i][0].record(stream)
+        launch(ctx)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    mean_ms = sum(ms) / K
+    r = result_from_bytes(buf)
+    grid = list(ctx.last_launch())
+    n, m = p.n, p.m
+    f32, f64, nbytes, checks = wide_work(n, m, r, ncand)
+    lam = r["lam"]
+    planted = p.meta["planted_lambda"]
+    lam_err = max(abs(a - b) for a, b in zip(lam, planted)) / max(abs(v) for v in planted)
+    # per-pass times of one launch on a tracing context
+    os.environ["PGDTO_TRACE"] = "1"
+    try:
+        tc = Context(0)
+    finally:
+        del os.environ["PGDTO_TRACE"]
+    launch(tc)
+    torch.cuda.synchronize()
+    recs = tc.trace_passes()
+    tc.close()
+    by = {}
+    for rec in recs:
+        by.setdefault(rec["phase"], []).append(rec)
+    phases = {k: {"passes": len(v), "loop_us": sum(q["loop_us"] for q in v) / len(v),
+                  "pass_us": sum(q["pass_us"] for q in v) / len(v)} for k, v in by.items()}
+    out = {"workload": f"project, {m} dense coupled rows (planted multiplier on every fourth row, seed "
+                       f"{WIDE_SEED}), 256x128x128 (n={n}), float32 streams",
+           "kernel": f"k_solve_wide<{(m + 15) // 16}>", "grid_tiles": grid, "launches": K,
+           "kernel_ms": {"mean": mean_ms, "p50": ms[K // 2], "max": ms[-1]},
+           "outcome": r["outcome"], "path": r["path"], "passes": r["passes"], "newton": r["iters_newton"],
+           "newton_passes": r["iters_ls"], "stage1_passes": r["iters_search"], "check_passes": checks,
+           "candidates": ncand, "lambda_rel_err_vs_planted": lam_err, "error": r["error"],
+           "roofline": {"bound": "mfma", "achieved": f32 / (mean_ms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK / 1e12,
+                        "unit": "TFLOP/s", "frac": f32 / (mean_ms * 1e-3) / MFMA_F32_PEAK,
+                        "flops_per_launch": f32, "dtype": "f32 (Jacobian sums A D A^T)",
+                        "note": "whole launch: the zero, Stage-1, check and final passes add time, not f32 flops"},
+           "check_f64": {"flops_per_launch": f64, "achieved": f64 / (mean_ms * 1e-3) / 1e12,
+                         "peak": MFMA_F64_PEAK / 1e12, "unit": "TFLOP/s"},
+           "hbm": {"bytes_per_launch": nbytes, "achieved": nbytes / (mean_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                   "unit": "GB/s", "frac": nbytes / (mean_ms * 1e-3) / HBM_PEAK},
+           "passes_traced": phases, "kernel_sha": kernel_sha(WIDE_SRC)}
+    if "newton" in phases:
+        t = phases["newton"]["loop_us"] * 1e-6
+        tp = phases["newton"]["pass_us"] * 1e-6
+        fl = n * m * (m + 1)
+        by_pass = n * ESZ * (m + 1)
+        out["newton_pass"] = {"flops": fl, "bytes": by_pass, "loop_us": t * 1e6, "pass_us": tp * 1e6,
+                              "mfma_frac_loop": fl / t / MFMA_F32_PEAK, "mfma_frac_pass": fl / tp / MFMA_F32_PEAK,
+                              "hbm_frac_loop": by_pass / t / HBM_PEAK, "hbm_frac_pass": by_pass / tp / HBM_PEAK}
+    return out
 
 
 # ---------------------------------------------------------------- one instance

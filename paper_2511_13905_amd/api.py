@@ -186,6 +186,28 @@ class Context:
         _check(min(n, 0), "pgdto_ctx_autotune_load")
         return n
 
+    def trace_passes(self, max_records=128):
+        """pgdto_trace_read: the per-pass records of the last one-instance
+        launch (a context created with PGDTO_TRACE=1; empty otherwise), as
+        dicts of the phase and the device-clock stamps in microseconds from
+        the pass start: loop (element loop done), go (the next pass may
+        start).  Reading clears the records."""
+        import ctypes
+        buf = (ctypes.c_uint64 * (8 * max_records))()
+        n = N.lib().pgdto_trace_read(self.h, buf, max_records)
+        _check(n if n < 0 else 0, "pgdto_trace_read")
+        names = {1: "pgd_r", 2: "zero", 3: "search", 4: "stage1", 5: "check", 6: "newton", 7: "final"}
+        out = []
+        for i in range(n):
+            r = list(buf[8 * i:8 * i + 8])
+            if r[0] == 0:
+                break
+            t0 = r[0] & ((1 << 56) - 1)
+            end = max(r[4], r[5])
+            out.append({"phase": names.get(r[0] >> 56, str(r[0] >> 56)), "loop_us": (r[1] - t0) / 100.0,
+                        "pass_us": (end - t0) / 100.0 if end else None})
+        return out
+
     def last_launch(self):
         """(workgroups, tiles) of the last launch on this context."""
         g, t = C.c_int32(), C.c_int32()

@@ -1092,6 +1092,7 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
   wait_own_stores();
   __syncthreads();
   if (!wide_barrier(sh, d, W, e1)) return false;
+  trace_put(d, pass, 2, clk());
   if (wid == 0) wide_raise_go(W, e1);
   else if (!wide_wait_go(sh, d, W, e1)) return false;
   // the partials of every tile are in memory
@@ -1111,10 +1112,12 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
   wait_own_stores();
   __syncthreads();
   if (!wide_barrier(sh, d, W, e2)) return false;
+  trace_put(d, pass, 3, clk());
   if (wid == 0) {
     for (int i = tid; i < nv; i += BLOCK) sh.tot[i] = fetch_published(W.tot + i);
     __syncthreads();
     wide_control(sh, d, W, ph);
+    trace_put(d, pass, 4, clk());
     // the command on every replica, then the go word
     constexpr int NW = REP_PAY + 2 * WM;
     for (int i = tid; i < NREP * NW; i += BLOCK) {
@@ -1130,6 +1133,7 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
     wait_own_stores();
     __syncthreads();
     wide_raise_go(W, e2);
+    trace_put(d, pass, 5, clk());
     return true;
   }
   if (!wide_wait_go(sh, d, W, e2)) return false;
@@ -1146,6 +1150,9 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
 }
 
 // ------------------------------------------------------------------ the solver
+// Per-pass trace records (contexts created with PGDTO_TRACE): [0] phase << 56
+// | start, [1] tiles done, [2] barrier A complete (every partial published),
+// [3] barrier B complete (every slice summed), [4] control done, [5] go raised.
 
 template <int MB>
 __device__ void solve_wide(ShW& sh, const Desc& d) {
@@ -1186,6 +1193,7 @@ __device__ void solve_wide(ShW& sh, const Desc& d) {
     const int ph = sh.ph;
     if (ph == PH_DONE) break;
     const int nv = wide_nv(ph, m, sh.aux);
+    trace_put(d, pass, 0, ((uint64_t)ph << 56) | (clk() & 0x00ffffffffffffffull));
     for (int tile = wid; tile < d.ntiles; tile += G) {
       const int64_t ts = (int64_t)tile * d.tile_elems;
       const int64_t te = min(ts + d.tile_elems, d.n);
@@ -1198,6 +1206,7 @@ __device__ void solve_wide(ShW& sh, const Desc& d) {
         default: tile_final<MB>(sh, d, ts, te, dst); break;
       }
     }
+    trace_put(d, pass, 1, clk());
     if (!wide_sync(sh, d, W, pass, ph, nv)) break;
   }
   report_error(d, d.result ? &((pgdto_result*)d.result)->error : nullptr);
