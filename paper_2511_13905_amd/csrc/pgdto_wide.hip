@@ -8,8 +8,9 @@
 //
 //  * lays a wave's data out as the matrix cores want it: lane (r, g), r =
 //    lane % 16, g = lane / 16, holds rows 16 bj + r (bj < MB) of 8
-//    consecutive elements e0 + 8 g + s.  That is both the A operand (row i =
-//    r, reduction index k = g) and the B operand (k = g, column j = r) of
+//    elements of a 32-element chunk (two float4s, see elem_off).  That is
+//    both the A operand (row i = r, reduction index k = g) and the B
+//    operand (k = g, column j = r) of
 //    v_mfma_f32_16x16x4_f32, so the free-masked tile F = D^(1/2) A of 32
 //    elements feeds 8 k-steps of F F^T on the MB (MB + 1) / 2 upper-triangle
 //    16 x 16 blocks with no data movement;
@@ -49,6 +50,12 @@ typedef double wf64x4 __attribute__((ext_vector_type(4)));
 constexpr int WCH = 32;      // elements per wave and chunk (one free-mask word)
 constexpr int WSL = 8;       // elements per lane and chunk
 constexpr int REP_PH = 1, REP_AUX = 2, REP_PAY = 4;   // words of a command replica after the go word
+constexpr int WNREP = 32;    // command replicas in use (of NREP): 8 workgroups read each at a full grid
+
+// The 8 elements of lane group g within a chunk: e0 + 4 g + s for s < 4 and
+// e0 + 16 + 4 g + (s - 4) for s >= 4, so that each load instruction covers 64
+// contiguous bytes of each of 16 rows (the groups' float4s side by side).
+__device__ __forceinline__ int elem_off(int g, int s) { return s < 4 ? 4 * g + s : 12 + 4 * g + s; }
 
 template <int MB> struct WN {
   static constexpr int NB = MB * (MB + 1) / 2;   // upper-triangle 16 x 16 blocks of J
@@ -131,6 +138,7 @@ struct ShW {
   double kappa, tol_n, tol_b, c1, c2, phi2, M0, gamma, res_inf, p2;
   int32_t max_newton, max_ls, max_search, ncp, search;
   int32_t have_best, ls, it, init, passes, path, outcome, nonfinite, s1passes, ls_total, cnext, decision;
+  uint64_t tmark[2];           // trace: totals in LDS, Newton direction solved
   union {
     float f[NWAVE * 2 * 256];  // two J blocks per round
     double d[NWAVE * 256];     // one float64 block per round, per-row values, scalars
@@ -143,11 +151,12 @@ struct ShW {
 // ... with the loads of its next chunk in flight while the current one is
 // used (two register buffers in turn), then the wave whose turn it is takes
 // the ragged last chunk, if any.  f(y, a, e0, whole): y[s], a[bj][s] of this
-// lane (zeros past the tile end and for rows >= m), e0 the chunk's first
-// element, whole = all 32 elements inside the tile.
+// lane for element e0 + elem_off(g, s) (zeros past the tile end and for rows
+// >= m), e0 the chunk's first element, whole = all 32 elements inside the tile.
 template <int MB, class F>
 __device__ __forceinline__ void wide_chunks(const Desc& d, int64_t ts, int64_t te, F&& f) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
   const int nfull = (int)((te - ts) / WCH);
   const bool ragged = (te - ts) % WCH != 0;
   const auto Y = gptr((const float*)d.y);
@@ -162,34 +171,47 @@ __device__ __forceinline__ void wide_chunks(const Desc& d, int64_t ts, int64_t t
     Arow[bj] = gptr((const float*)d.A + (int64_t)row * d.lda);
   }
   auto load_whole = [&](int c, float (&yv)[WSL], float (&av)[MB][WSL]) __attribute__((always_inline)) {
-    const int64_t eb = ts + (int64_t)c * WCH + WSL * g;
+    const int64_t eb = ts + (int64_t)c * WCH + 4 * g;
     ld_vec_whole<float>(Y, eb, yv);
-    ld_vec_whole<float>(Y, eb + 4, yv + 4);
+    ld_vec_whole<float>(Y, eb + 16, yv + 4);
 #pragma unroll
     for (int bj = 0; bj < MB; ++bj) {
       ld_vec_whole<float>(Arow[bj], eb, av[bj]);
-      ld_vec_whole<float>(Arow[bj], eb + 4, av[bj] + 4);
+      ld_vec_whole<float>(Arow[bj], eb + 16, av[bj] + 4);
     }
+  };
+  // the padded rows are zeroed when a buffer is used, not when it is loaded
+  // (a select right after the loads would wait for them and stall the prefetch)
+  const bool any_pad = 16 * MB > m;
+  auto use = [&](float (&yv)[WSL], float (&av)[MB][WSL], int c) __attribute__((always_inline)) {
+    if (any_pad) {
 #pragma unroll
-    for (int s = 0; s < WSL; ++s) av[MB - 1][s] = pad ? 0.f : av[MB - 1][s];
+      for (int s = 0; s < WSL; ++s) av[MB - 1][s] = pad ? 0.f : av[MB - 1][s];
+    }
+    f(yv, av, ts + (int64_t)c * WCH, true);
   };
   float y0[WSL], a0[MB][WSL], y1[WSL], a1[MB][WSL];
   int c = w;
   if (c < nfull) load_whole(c, y0, a0);
+  // sched_barrier: the next chunk's loads stay ahead of the current chunk's
+  // work (left alone, the scheduler sinks them behind it to save registers,
+  // which leaves no load in flight while a chunk is being used)
   while (c < nfull) {
     if (c + NWAVE < nfull) load_whole(c + NWAVE, y1, a1);
-    f(y0, a0, ts + (int64_t)c * WCH, true);
+    __builtin_amdgcn_sched_barrier(0);
+    use(y0, a0, c);
     c += NWAVE;
     if (c >= nfull) break;
     if (c + NWAVE < nfull) load_whole(c + NWAVE, y0, a0);
-    f(y1, a1, ts + (int64_t)c * WCH, true);
+    __builtin_amdgcn_sched_barrier(0);
+    use(y1, a1, c);
     c += NWAVE;
   }
   if (ragged && w == nfull % NWAVE) {
-    const int64_t e0 = ts + (int64_t)nfull * WCH, eb = e0 + WSL * g;
+    const int64_t e0 = ts + (int64_t)nfull * WCH;
 #pragma unroll
     for (int s = 0; s < WSL; ++s) {
-      const int64_t e = eb + s;
+      const int64_t e = e0 + elem_off(g, s);
       const int64_t ec = e < te ? e : te - 1;
       const float v = Y[ec];
       y0[s] = e < te ? v : 0.f;
@@ -329,13 +351,12 @@ __device__ __forceinline__ void tile_zero(ShW& sh, const Desc& d, int64_t ts, in
     for (int k = 0; k < 6; ++k) acc[bj][k] = (k == 2) ? -INFINITY : 0.0;
   double bad[1] = {0.0};
   wide_chunks<MB>(d, ts, te, [&](const float (&yv)[WSL], const float (&av)[MB][WSL], int64_t e0, bool whole) __attribute__((always_inline)) {
-    const int64_t eb = e0 + WSL * g;
 #pragma unroll
     for (int s = 0; s < WSL; ++s) {
       const double y = (double)yv[s];
       const double x0 = clampd(y, lo, hi);
       const bool fr = (y >= lo) && (y <= hi);
-      if (r == 0 && (whole || eb + s < te) && !isfinite(y)) bad[0] += 1.0;
+      if (r == 0 && (whole || e0 + elem_off(g, s) < te) && !isfinite(y)) bad[0] += 1.0;
 #pragma unroll
       for (int bj = 0; bj < MB; ++bj) {
         const double a = (double)av[bj][s];
@@ -411,12 +432,12 @@ __device__ __forceinline__ void tile_check(ShW& sh, const Desc& d, int64_t ts, i
 #pragma unroll
   for (int bk = 0; bk < MB; ++bk) acc[bk] = wf64x4{0.0, 0.0, 0.0, 0.0};
   wide_chunks<MB>(d, ts, te, [&](const float (&yv)[WSL], const float (&av)[MB][WSL], int64_t e0, bool whole) __attribute__((always_inline)) {
-    const int64_t eb = e0 + WSL * g;
+    const int64_t eb = e0 + 4 * g;
     float ac[WSL];
     if (whole) {
       if (crow >= 0) {
         ld_vec_whole<float>(Ac, eb, ac);
-        ld_vec_whole<float>(Ac, eb + 4, ac + 4);
+        ld_vec_whole<float>(Ac, eb + 16, ac + 4);
       } else {
 #pragma unroll
         for (int s = 0; s < WSL; ++s) ac[s] = 0.f;
@@ -424,7 +445,7 @@ __device__ __forceinline__ void tile_check(ShW& sh, const Desc& d, int64_t ts, i
     } else {
 #pragma unroll
       for (int s = 0; s < WSL; ++s) {
-        const int64_t e = eb + s;
+        const int64_t e = e0 + elem_off(g, s);
         const int64_t ec = e < te ? e : te - 1;
         float v = 0.f;
         if (crow >= 0) v = Ac[ec];
@@ -508,7 +529,6 @@ __device__ __forceinline__ void tile_final(ShW& sh, const Desc& d, int64_t ts, i
   }
   double sc[4] = {0.0, 0.0, 0.0, 0.0};   // free count, (pgd terms unused), |x - y|^2
   wide_chunks<MB>(d, ts, te, [&](const float (&yv)[WSL], const float (&av)[MB][WSL], int64_t e0, bool whole) __attribute__((always_inline)) {
-    const int64_t eb = e0 + WSL * g;
     float xo[WSL];
     uint32_t bits = 0;
 #pragma unroll
@@ -519,7 +539,7 @@ __device__ __forceinline__ void tile_final(ShW& sh, const Desc& d, int64_t ts, i
       p = row_sum16(p);
       const double z = (double)yv[s] - p;
       xo[s] = (float)clampd(z, lo, hi);
-      const bool valid = whole || eb + s < te;
+      const bool valid = whole || e0 + elem_off(g, s) < te;
       if (valid && z >= lo && z <= hi) bits |= 1u << s;
       const double xr = (double)xo[s];
 #pragma unroll
@@ -533,16 +553,23 @@ __device__ __forceinline__ void tile_final(ShW& sh, const Desc& d, int64_t ts, i
     if (whole) {
       if (r < 2) {
         const wf32x4 v = (r == 0) ? wf32x4{xo[0], xo[1], xo[2], xo[3]} : wf32x4{xo[4], xo[5], xo[6], xo[7]};
-        *reinterpret_cast<__attribute__((address_space(1))) wf32x4*>(gptr_w(X) + eb + 4 * r) = v;
+        *reinterpret_cast<__attribute__((address_space(1))) wf32x4*>(gptr_w(X) + e0 + 4 * g + 16 * r) = v;
       }
     } else if (r == 0) {
 #pragma unroll
-      for (int s = 0; s < WSL; ++s)
-        if (eb + s < te) gptr_w(X)[eb + s] = xo[s];
+      for (int s = 0; s < WSL; ++s) {
+        const int64_t e = e0 + elem_off(g, s);
+        if (e < te) gptr_w(X)[e] = xo[s];
+      }
     }
     if (d.free_mask) {
-      const uint32_t word = (uint32_t)__shfl((int)bits, 0, 64) | ((uint32_t)__shfl((int)bits, 16, 64) << 8) |
-                            ((uint32_t)__shfl((int)bits, 32, 64) << 16) | ((uint32_t)__shfl((int)bits, 48, 64) << 24);
+      // bit elem_off(g, s) of the chunk's word: the group's low nibble at 4 g, high nibble at 16 + 4 g
+      uint32_t word = 0;
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        const uint32_t b = (uint32_t)__shfl((int)bits, 16 * gg, 64);
+        word |= ((b & 0xFu) << (4 * gg)) | ((b >> 4) << (16 + 4 * gg));
+      }
       if (lane == 0) d.free_mask[e0 >> 5] = word;
     }
   });
@@ -659,6 +686,7 @@ __device__ void wide_direction(ShW& sh, double* J, int m) {
     if (ln < p) sh.delta[sh.sidx[ln]] = v;
   }
   __syncthreads();
+  if (tid == 0) sh.tmark[1] = clk();
 }
 
 // Accept (lam, h, J) as the iterate: stop (returns PH_FINAL, payload = the
@@ -1058,7 +1086,7 @@ __device__ __forceinline__ bool wide_barrier(ShW& sh, const Desc& d, const WSync
 // A worker's wait for the go word of epoch e on its replica.
 __device__ __forceinline__ bool wide_wait_go(ShW& sh, const Desc& d, const WSync& W, uint64_t e) {
   const int wid = wg_id(d);
-  uint64_t* my = W.rep + (size_t)(wid % NREP) * WREP;
+  uint64_t* my = W.rep + (size_t)(wid % WNREP) * WREP;
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
     bool ok = true;
@@ -1079,7 +1107,7 @@ __device__ __forceinline__ bool wide_wait_go(ShW& sh, const Desc& d, const WSync
 }
 
 __device__ __forceinline__ void wide_raise_go(const WSync& W, uint64_t e) {
-  if (threadIdx.x < NREP)
+  if (threadIdx.x < WNREP)
     __hip_atomic_store(W.rep + (size_t)threadIdx.x * WREP, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -1116,11 +1144,18 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
   if (wid == 0) {
     for (int i = tid; i < nv; i += BLOCK) sh.tot[i] = fetch_published(W.tot + i);
     __syncthreads();
+    if (tid == 0) { sh.tmark[0] = clk(); sh.tmark[1] = 0; }
     wide_control(sh, d, W, ph);
     trace_put(d, pass, 4, clk());
-    // the command on every replica, then the go word
-    constexpr int NW = REP_PAY + 2 * WM;
-    for (int i = tid; i < NREP * NW; i += BLOCK) {
+    trace_put(d, pass, 6, sh.tmark[0]);
+    trace_put(d, pass, 7, sh.tmark[1]);
+    // the command on every replica (the payload words the next pass reads),
+    // then the go word
+    const int nph = sh.ph;
+    const int npay = nph == PH_STAGE1 ? NT * m : nph == PH_CHECK ? 2 * WCAND
+                     : (nph == PH_NEWTON || nph == PH_FINAL) ? m : 0;
+    const int NW = REP_PAY + npay;
+    for (int i = tid; i < WNREP * NW; i += BLOCK) {
       const int rp = i / NW, k = i - rp * NW;
       uint64_t v;
       if (k == 0) continue;
@@ -1137,7 +1172,7 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
     return true;
   }
   if (!wide_wait_go(sh, d, W, e2)) return false;
-  const uint64_t* my = W.rep + (size_t)(wid % NREP) * WREP;
+  const uint64_t* my = W.rep + (size_t)(wid % WNREP) * WREP;
   if (tid == 0) {
     sh.ph = (int32_t)__hip_atomic_load(my + REP_PH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sh.aux = (int32_t)__hip_atomic_load(my + REP_AUX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1152,7 +1187,8 @@ __device__ bool wide_sync(ShW& sh, const Desc& d, const WSync& W, int pass, int 
 // ------------------------------------------------------------------ the solver
 // Per-pass trace records (contexts created with PGDTO_TRACE): [0] phase << 56
 // | start, [1] tiles done, [2] barrier A complete (every partial published),
-// [3] barrier B complete (every slice summed), [4] control done, [5] go raised.
+// [3] barrier B complete (every slice summed), [4] control done, [5] go
+// raised, [6] totals in LDS (control starts), [7] last Newton direction solved.
 
 template <int MB>
 __device__ void solve_wide(ShW& sh, const Desc& d) {
@@ -1193,7 +1229,8 @@ __device__ void solve_wide(ShW& sh, const Desc& d) {
     const int ph = sh.ph;
     if (ph == PH_DONE) break;
     const int nv = wide_nv(ph, m, sh.aux);
-    trace_put(d, pass, 0, ((uint64_t)ph << 56) | (clk() & 0x00ffffffffffffffull));
+    const uint64_t t_pass0 = clk();
+    trace_put(d, pass, 0, ((uint64_t)ph << 56) | (t_pass0 & 0x00ffffffffffffffull));
     for (int tile = wid; tile < d.ntiles; tile += G) {
       const int64_t ts = (int64_t)tile * d.tile_elems;
       const int64_t te = min(ts + d.tile_elems, d.n);
@@ -1207,7 +1244,9 @@ __device__ void solve_wide(ShW& sh, const Desc& d) {
       }
     }
     trace_put(d, pass, 1, clk());
+    trace_wg(d, pass, t_pass0, clk());
     if (!wide_sync(sh, d, W, pass, ph, nv)) break;
+    trace_wg_go(d, pass, clk());
   }
   report_error(d, d.result ? &((pgdto_result*)d.result)->error : nullptr);
 }
