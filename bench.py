@@ -74,6 +74,16 @@ MEASURED_TRAFFIC = {
 }
 
 
+# the same for the wide coupled kernel's launches (one projection each), by row count
+# (profiles/k_solve_wide_f32_many_rows_hbm_traffic.md)
+WIDE_MEASURED_TRAFFIC = {
+    64: {"kernel_sha": "c5104efd19b4f7a8", "bytes_per_launch": 20453444473, "read": 20303870320,
+         "written": 149574153},
+    32: {"kernel_sha": "c5104efd19b4f7a8", "bytes_per_launch": 6724215576, "read": 6685580513,
+         "written": 38635063},
+}
+
+
 def kernel_sha(files=None):
     import hashlib
     h = hashlib.sha256()
@@ -459,8 +469,13 @@ def wide_bench(ctx, p, ncand, args):
            "check_f64": {"flops_per_launch": f64, "achieved": f64 / (mean_ms * 1e-3) / 1e12,
                          "peak": MFMA_F64_PEAK / 1e12, "unit": "TFLOP/s"},
            "hbm": {"bytes_per_launch": nbytes, "achieved": nbytes / (mean_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
-                   "unit": "GB/s", "frac": nbytes / (mean_ms * 1e-3) / HBM_PEAK},
+                   "unit": "GB/s", "frac": nbytes / (mean_ms * 1e-3) / HBM_PEAK, "traffic": None},
            "passes_traced": phases, "kernel_sha": kernel_sha(WIDE_SRC)}
+    tr = WIDE_MEASURED_TRAFFIC.get(m)
+    if tr and tr["kernel_sha"] == out["kernel_sha"] and p.meta.get("seed") == WIDE_SEED:
+        out["hbm"]["traffic"] = tr["bytes_per_launch"]
+        out["hbm"]["traffic_read"] = tr["read"]
+        out["hbm"]["traffic_written"] = tr["written"]
     if "newton" in phases:
         t = phases["newton"]["loop_us"] * 1e-6
         tp = phases["newton"]["pass_us"] * 1e-6
