@@ -132,7 +132,7 @@ struct Sh1D {
 // instance has rows held at equality (the zero pass adds the opposite
 // direction's bracket); CP: the free-set compaction is on.  Separate
 // instantiations, so that the common case keeps its register allocation.
-template <typename T, bool EQ = false, bool CP = false, int SU = 2>
+template <typename T, bool EQ = false, bool CP = false, int SU = 2, bool NT = false>
 __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   constexpr int V = VT<T>::N;
   constexpr int SU1 = SU > 2 ? SU / 2 : 1;     // for the 3- to 5-stream passes
@@ -182,7 +182,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
       // g.(g - g_prev), |g_prev|^2, |g|_inf, a.rho_t
       if (d.zero_step) {
         const T* ptr[3] = {(const T*)d.rho, (const T*)d.grad, A};
-        stream_tile<T, 3, SU1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+        stream_tile<T, 3, SU1, NT>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
@@ -194,7 +194,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
         });
       } else {
         const T* ptr[5] = {(const T*)d.rho, (const T*)d.grad, A, (const T*)d.rho_prev, (const T*)d.grad_prev};
-        stream_tile<T, 5, SU1>(g, d.n, ptr, [&](const T (&b)[5][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+        stream_tile<T, 5, SU1, NT>(g, d.n, ptr, [&](const T (&b)[5][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < V; ++q) {
             if (!(mask & (1u << q))) continue;
@@ -346,7 +346,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               if (d.pgd) {
                 T tmp[RS][1][V];
                 const T* pa[1] = {A};
-                ld_slots<T, RS, 1>(pa, re0, d.n, tmp);
+                ld_slots<T, RS, 1, NT>(pa, re0, d.n, tmp);
   #pragma unroll
                 for (int k = 0; k < RS; ++k)
   #pragma unroll
@@ -354,7 +354,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               } else {
                 T tmp[RS][2][V];
                 const T* pa[2] = {A, Y};
-                ld_slots<T, RS, 2>(pa, re0, d.n, tmp);
+                ld_slots<T, RS, 2, NT>(pa, re0, d.n, tmp);
   #pragma unroll
                 for (int k = 0; k < RS; ++k)
   #pragma unroll
@@ -376,7 +376,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
                 }
                 T tmp[1][3][V];
                 const T* pa[3] = {(const T*)d.rho, (const T*)d.grad, d.zero_step ? (const T*)d.rho : (const T*)d.dir};
-                ld_slots<T, 1, 3>(pa, &e0, d.n, tmp);
+                ld_slots<T, 1, 3, NT>(pa, &e0, d.n, tmp);
   #pragma unroll
                 for (int q = 0; q < V; ++q) {
                   nr[q] = tmp[0][0][q];
@@ -439,18 +439,18 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             };
             if (d.zero_step) {
               const T* ptr[3] = {A, (const T*)d.rho, (const T*)d.grad};
-              stream_tile<T, 3, SU1>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+              stream_tile<T, 3, SU1, NT>(g, d.n, ptr, [&](const T (&b)[3][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
                 body(b[0], b[1], b[2], nullptr, e0, mask, full);
               });
             } else {
               const T* ptr[4] = {A, (const T*)d.rho, (const T*)d.grad, (const T*)d.dir};
-              stream_tile<T, 4, SU1>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
+              stream_tile<T, 4, SU1, NT>(g, d.n, ptr, [&](const T (&b)[4][V], int64_t e0, uint32_t mask, bool full) __attribute__((always_inline)) {
                 body(b[0], b[1], b[2], b[3], e0, mask, full);
               });
             }
           } else {
             const T* ptr[2] = {Y, A};
-            stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+            stream_tile<T, 2, SU, NT>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
   #pragma unroll
               for (int q = 0; q < V; ++q)
                 if (mask & (1u << q)) zero_elem(f64(b[0][q]), f64(b[1][q]));
@@ -496,7 +496,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               for (int q = 0; q < V; ++q) elem(ry[k][q], ra[k][q], q & 1);
           } else {
             const T* ptr[2] = {Y, A};
-            stream_tile<T, 2, SU>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
+            stream_tile<T, 2, SU, NT>(g, d.n, ptr, [&](const T (&b)[2][V], int64_t, uint32_t mask, bool) __attribute__((always_inline)) {
 #pragma unroll
               for (int q = 0; q < V; ++q) {
                 const bool ok = (mask >> q) & 1u;
@@ -559,8 +559,8 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                   const int64_t e0 = base + (int64_t)(k0 + u) * (BLOCK * V);
-                  ld_vec_whole<T>(gptr(Y), e0, b[u][0]);
-                  ld_vec_whole<T>(gptr(A), e0, b[u][1]);
+                  ld_vec_whole<T, NT>(gptr(Y), e0, b[u][0]);
+                  ld_vec_whole<T, NT>(gptr(A), e0, b[u][1]);
                 }
 #pragma unroll
                 for (int u = 0; u < 2; ++u) slot_c(b[u][0], b[u][1], two_c);
@@ -626,7 +626,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
               if (!rmask(k)) e0 = d.n;          // reads zeros
               T tmp[1][1][V];
               const T* pa[1] = {R};
-              ld_slots<T, 1, 1>(pa, &e0, d.n, tmp);
+              ld_slots<T, 1, 1, NT>(pa, &e0, d.n, tmp);
 #pragma unroll
               for (int q = 0; q < V; ++q) rnext[q] = tmp[0][0][q];
             }
@@ -661,7 +661,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
             int64_t le0 = nany ? ne0 : d.n;    // reads zeros
             T tmp[1][3][V];
             const T* pa[3] = {Y, A, d.pgd ? R : Y};
-            ld_slots<T, 1, 3>(pa, &le0, d.n, tmp);
+            ld_slots<T, 1, 3, NT>(pa, &le0, d.n, tmp);
 #pragma unroll
             for (int q = 0; q < V; ++q) {
               ny[q] = tmp[0][0][q];
@@ -1817,8 +1817,8 @@ union ShSrv {
 __shared__ ShSrv srv_sh;
 __shared__ Desc srv_sd;
 
-template <bool EQ, bool CP>
-__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ, CP>(srv_sh.s1, srv_sd); }
+template <bool EQ, bool CP, bool NT = false>
+__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ, CP, 2, NT>(srv_sh.s1, srv_sd); }
 template <int M>
 __device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd); }
 
@@ -1989,11 +1989,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
         default: srv_solve_coupled<8>(); break;
       }
     } else {
+      // Algorithm 3 steps stream five arrays per instance: non-temporal loads
+      // (the compaction variant re-reads the pairs it keeps: ordinary loads)
       const bool cp = srv_sd.compact && srv_sd.cbuf;
+      const bool nt = a.is_pgd && !cp;
       if (srv_sd.eq_mask) {
-        if (cp) srv_solve_1d<true, true>(); else srv_solve_1d<true, false>();
+        if (cp) srv_solve_1d<true, true>(); else if (nt) srv_solve_1d<true, false, true>(); else srv_solve_1d<true, false>();
       } else {
-        if (cp) srv_solve_1d<false, true>(); else srv_solve_1d<false, false>();
+        if (cp) srv_solve_1d<false, true>(); else if (nt) srv_solve_1d<false, false, true>(); else srv_solve_1d<false, false>();
       }
     }
     __syncthreads();
