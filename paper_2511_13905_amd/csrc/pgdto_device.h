@@ -219,7 +219,9 @@ __device__ __forceinline__ void block_to_part(const double (&acc)[NV], int nv, u
       r = mx ? wave_max(r) : wave_sum(r);
       if (lane == 0) publish(&pb[v * TILES_PAD + tile], r);
     }
-    if (c + NWAVE >= NV) wait_own_stores();   // before the last barrier
+    // no wait for the stores here: a workgroup reduces many tiles per pass
+    // and a wait would drain its loads and stores at every tile; the grid
+    // barrier waits for them once, before the pass's flag
     __syncthreads();
   }
 }
@@ -338,13 +340,45 @@ __device__ __forceinline__ bool grid_reduce(const Desc& d, uint64_t epoch, const
   const int wid = wg_id(d);
   const int ntot = nseg * nv;
   const bool in_rep = ntot <= REP_VALS;
+  // every wave's stores of this pass (tile partials, streamed outputs) are
+  // complete before the barrier that precedes the flag
+  wait_own_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
     *abort_flag = 0;
-    // the partials of every wave are in memory (block_to_part waited for them)
+    // the partials of every wave are in memory
     __hip_atomic_store(&W.flags[(size_t)wid * FLAG_STRIDE], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
+  if (d.allred) {
+    // every workgroup waits for every flag, then reduces the partials itself
+    // in the same fixed order (so every workgroup holds the same bits); a
+    // workgroup writes this buffer again two passes later, after every
+    // workgroup has raised the next pass's flag, which it does only after
+    // this read
+    bool ok = true;
+    for (int w = threadIdx.x; w < G && ok; w += BLOCK) {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&W.flags[(size_t)w * FLAG_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT || __hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == d.epoch0) {
+          ok = false;
+          break;
+        }
+      }
+    }
+    if (!ok) atomicOr(abort_flag, 1);
+    __syncthreads();
+    if (*abort_flag) {
+      if (threadIdx.x == 0) __hip_atomic_store(W.err, d.epoch0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    trace_put(d, pass_no, 2, clk());
+    trace_wg_go(d, pass_no, clk());
+    reduce_tiles(pb, nv, maxmask, d.tile_base, nseg, tot);
+    trace_put(d, pass_no, 3, clk());
+    return true;
+  }
   if (wid == 0) {
     bool ok = true;
     for (int w = threadIdx.x; w < G && ok; w += BLOCK) {

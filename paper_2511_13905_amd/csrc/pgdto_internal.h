@@ -73,6 +73,11 @@ struct Desc {
   double* wide;          // workspace of the wide coupled kernel (m > SMALL_M), else NULL
   uint64_t epoch0;       // epoch base (pass p publishes epoch0 + p + 1): from the arrival
                          // door's generation in one-instance launches, per job in the server
+  int32_t allred;        // 1: every workgroup waits for every flag and reduces the partials
+                         // itself (batch slots of a few workgroups); 0: workgroup 0 reduces
+                         // them and publishes the totals with the go word
+  int32_t buf0;          // partial-sum buffer of the first pass (a batch slot alternates the
+                         // two buffers from one instance to the next)
   void* result;          // pgdto_result (pgd: pgdto_pgd_out)
   uint64_t* trace;       // optional [TRACE_MAX][4] per-pass timestamps (workgroup 0)
 };

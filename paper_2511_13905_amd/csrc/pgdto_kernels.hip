@@ -133,7 +133,7 @@ struct Sh1D {
 // direction's bracket); CP: the free-set compaction is on.  Separate
 // instantiations, so that the common case keeps its register allocation.
 template <typename T, bool EQ = false, bool CP = false, int SU = 2, bool NT = false>
-__device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
+__device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d, int32_t* buf_end = nullptr) {
   constexpr int V = VT<T>::N;
   constexpr int SU1 = SU > 2 ? SU / 2 : 1;     // for the 3- to 5-stream passes
   const int tid = threadIdx.x;
@@ -157,7 +157,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   }
   __syncthreads();
 
-  int buf = 0;
+  int buf = d.buf0 & 1;
   const T* A = (const T*)d.A;
   // CP: the instantiation with the free-set compaction (a request asks for
   // it with compact != 0 and scratch); without it every compaction branch
@@ -906,6 +906,7 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d) {
   int32_t* errp = nullptr;
   if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
   report_error(d, errp);
+  if (buf_end && threadIdx.x == 0) *buf_end = buf;     // the next instance of a batch slot starts there
 }
 
 // Zero the free-mask words of this workgroup's tiles (before the first grid
@@ -1223,7 +1224,7 @@ __device__ __forceinline__ int newton_after_trial(ShC& sh, const double (&tr)[M]
 }
 
 template <typename T, int M>
-__device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
+__device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d, int32_t* buf_end = nullptr) {
   constexpr int V = VT<T>::N;
   using C = CN<M>;
   const int tid = threadIdx.x;
@@ -1253,7 +1254,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
   }
   __syncthreads();
 
-  int buf = 0;
+  int buf = d.buf0 & 1;
   const T* Arow[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) Arow[j] = (const T*)d.A + (int64_t)j * d.lda;
@@ -1777,6 +1778,7 @@ __device__ __forceinline__ void solve_coupled(ShC& sh, const Desc& d) {
   int32_t* errp = nullptr;
   if (d.result) errp = d.pgd ? &((pgdto_pgd_out*)d.result)->proj.error : &((pgdto_result*)d.result)->error;
   report_error(d, errp);
+  if (buf_end && threadIdx.x == 0) *buf_end = buf;     // the next instance of a batch slot starts there
 }
 
 template <typename T, int M>
@@ -1817,10 +1819,11 @@ union ShSrv {
 __shared__ ShSrv srv_sh;
 __shared__ Desc srv_sd;
 
+__shared__ int32_t srv_buf_end;     // partial-sum buffer after the last solve
 template <bool EQ, bool CP, bool NT = false>
-__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ, CP, 2, NT>(srv_sh.s1, srv_sd); }
+__device__ __noinline__ void srv_solve_1d() { solve_1d<float, EQ, CP, 2, NT>(srv_sh.s1, srv_sd, &srv_buf_end); }
 template <int M>
-__device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd); }
+__device__ __noinline__ void srv_solve_coupled() { solve_coupled<float, M>(srv_sh.sc, srv_sd, &srv_buf_end); }
 
 
 __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
@@ -1954,6 +1957,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
   const int W = a.wg_per_slot;
   const int slot = (int)blockIdx.x / W;
   if (slot >= a.slots) return;
+  int32_t nbuf = 0;          // partial-sum buffer of the slot's next pass
   for (int k = 0;; ++k) {
     const int64_t i = (int64_t)slot + (int64_t)k * a.slots;
     if (i >= a.count) return;
@@ -1973,6 +1977,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
         sd.pgd = a.is_pgd;
         sd.result = a.is_pgd ? (void*)((pgdto_pgd_out*)a.results + i) : (void*)((pgdto_result*)a.results + i);
         sd.trace = nullptr;
+        // the one-row solver's few partials per tile are reduced by every
+        // workgroup of the slot; the buffers keep alternating across instances
+        sd.allred = sd.kind != PGDTO_COUPLED;
+        sd.buf0 = nbuf;
       }
       __syncthreads();
     }
@@ -2000,6 +2008,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
       }
     }
     __syncthreads();
+    nbuf = srv_buf_end;
   }
 }
 
