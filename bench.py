@@ -69,18 +69,18 @@ KERNEL_SRC = [os.path.join(CSRC, f) for f in ("pgdto_internal.h", "pgdto_device.
 WIDE_SRC = [os.path.join(CSRC, f) for f in ("pgdto_internal.h", "pgdto_device.h", "pgdto_wide.hip")]
 MEASURED_TRAFFIC = {
     # profiles/k_batch_f32_pgd_compliance_b16_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "e5736559fbdca668", "bytes_per_launch": 6547038350,
-                       "read": 5644689496, "written": 902348854, "instances": 16},
+    "pgd_compliance": {"kernel_sha": "933fa44a2c99ea89", "bytes_per_launch": 6596505503,
+                       "read": 5736478591, "written": 860026912, "instances": 16},
 }
 
 
 # the same for the wide coupled kernel's launches (one projection each), by row count
 # (profiles/k_solve_wide_f32_many_rows_hbm_traffic.md)
 WIDE_MEASURED_TRAFFIC = {
-    64: {"kernel_sha": "c5104efd19b4f7a8", "bytes_per_launch": 20453444473, "read": 20303870320,
-         "written": 149574153},
-    32: {"kernel_sha": "c5104efd19b4f7a8", "bytes_per_launch": 6724215576, "read": 6685580513,
-         "written": 38635063},
+    64: {"kernel_sha": "884988942cb77054", "bytes_per_launch": 20455012991, "read": 20305437750,
+         "written": 149575241},
+    32: {"kernel_sha": "884988942cb77054", "bytes_per_launch": 6722674577, "read": 6684039560,
+         "written": 38635017},
 }
 
 
