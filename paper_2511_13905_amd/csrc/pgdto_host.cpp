@@ -357,6 +357,10 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   d.wg_base = 0;
   d.wg_count = grid;
   d.door_wait = c->door_wait;
+  // every workgroup reduces the pass partials itself (one round trip less per
+  // pass than workgroup 0 publishing totals and a go word)
+  d.allred = grid <= ALLRED_MAX_WG ? 1 : 0;
+  d.buf0 = 0;
   // an ordinary launch: the kernel's arrival door admits the workgroups that
   // are running together (normally all of them) and sends late ones home
   hipError_t e = launch_solve(d, grid, s, false);

@@ -25,6 +25,11 @@ constexpr int REP_WORDS = 128;             // 1 KiB per copy: go word + up to 12
 // door of one-instance launches
 constexpr size_t SYNC_WORDS = (size_t)GMAX * 16 + (size_t)NREP * REP_WORDS + 16 + TOT_MAX + 32;   // uint64 words
 
+// Largest workgroup count for which every workgroup reads every flag and
+// every tile partial of a pass itself (beyond it the polls of the same lines
+// would queue up; workgroup 0 then reduces alone and broadcasts the totals).
+constexpr int ALLRED_MAX_WG = 256;
+
 // Bounded spin of the grid barrier: about a second of waiting before the
 // workgroup gives up, flags PGDTO_ERR_TIMEOUT and leaves the kernel.
 constexpr uint32_t SPIN_LIMIT = 1u << 20;
@@ -74,7 +79,7 @@ struct Desc {
   uint64_t epoch0;       // epoch base (pass p publishes epoch0 + p + 1): from the arrival
                          // door's generation in one-instance launches, per job in the server
   int32_t allred;        // 1: every workgroup waits for every flag and reduces the partials
-                         // itself (batch slots of a few workgroups); 0: workgroup 0 reduces
+                         // itself (up to ALLRED_MAX_WG workgroups); 0: workgroup 0 reduces
                          // them and publishes the totals with the go word
   int32_t buf0;          // partial-sum buffer of the first pass (a batch slot alternates the
                          // two buffers from one instance to the next)

@@ -1841,6 +1841,7 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
   const int slot = (int)blockIdx.x / W;
   const int vb = (int)blockIdx.x - slot * W;
   uint64_t* sw = a.slot_words + (size_t)slot * 16;
+  int32_t nbuf = 0;          // partial-sum buffer of the slot's next pass
   for (uint64_t r = 1;; ++r) {
     const uint64_t seq = a.round0 + r;
     if (threadIdx.x == 0) {
@@ -1903,6 +1904,12 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
         sd.sync = a.sync + (size_t)slot * a.sync_stride;
         sd.result = sd.pgd ? (void*)(a.results + q) : (void*)&a.results[q].proj;
         sd.trace = nullptr;
+        // every workgroup of the slot reduces the pass partials itself; the
+        // two buffers keep alternating across the slot's jobs (a workgroup
+        // that starts the next job cannot overwrite partials another
+        // workgroup of the slot is still reading)
+        sd.allred = W <= ALLRED_MAX_WG ? 1 : 0;
+        sd.buf0 = nbuf;
       }
       __syncthreads();
     }
@@ -1927,6 +1934,7 @@ __global__ __launch_bounds__(BLOCK) void k_server(const SrvArgs) {
       }
     }
     __syncthreads();
+    nbuf = srv_buf_end;
     if (vb == 0 && threadIdx.x == 0) {
       // the result (written by this workgroup) before the completion word
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
@@ -1977,9 +1985,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchArgs) {
         sd.pgd = a.is_pgd;
         sd.result = a.is_pgd ? (void*)((pgdto_pgd_out*)a.results + i) : (void*)((pgdto_result*)a.results + i);
         sd.trace = nullptr;
-        // the one-row solver's few partials per tile are reduced by every
-        // workgroup of the slot; the buffers keep alternating across instances
-        sd.allred = sd.kind != PGDTO_COUPLED;
+        // every workgroup of the slot reduces the pass partials itself; the
+        // two buffers keep alternating across the slot's instances
+        sd.allred = W <= ALLRED_MAX_WG ? 1 : 0;
         sd.buf0 = nbuf;
       }
       __syncthreads();
@@ -2185,6 +2193,8 @@ extern "C" int pgdto_project_noalloc(const pgdto_problem* prob, const pgdto_para
   d.wg_base = 0;
   d.wg_count = grid;
   d.door_wait = DOOR_WAIT_DEFAULT;
+  d.allred = grid <= ALLRED_MAX_WG ? 1 : 0;   // as the other one-instance launches
+  d.buf0 = 0;
   if (launch_solve(d, grid, s, false) != hipSuccess) {
     (void)hipGetLastError();
     (void)launch_mark_error(result_dev, 0, s);
