@@ -57,6 +57,9 @@ def parse():
                     help="row counts of the many-row coupled leg (wide kernel), comma separated; empty: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--single-only", action="store_true",
+                    help="run only the one-instance launches (no batch, server or wide legs): the command "
+                         "the one-instance kernel profiles are taken with")
     return ap.parse_args()
 
 
@@ -265,6 +268,14 @@ def main():
                     "volcom": "project, volume + centre-of-mass m=5 coupled, 192x96x96 (n=1769472), "
                               "even seeds feasible / odd seeds infeasible"}[wl]
         workload = f"{workload} on {B} distinct instances per launch, float32"
+    if args.single_only:
+        out = {"workload": workload.replace(f" on {B} distinct instances per launch", "") + ", one-instance launches",
+               "single_instance": single_bench(ctx, insts, is_pgd, n, rows, args), "kernel_sha": kernel_sha()}
+        close_all()
+        del insts
+        torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
     nres = result_nbytes(pgd=is_pgd)
     res_buf = torch.zeros(nres * B, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
