@@ -504,7 +504,9 @@ int pgdto_version(void);
  * context creation, every launch records, per streaming pass, eight 64-bit
  * values on the device's 100 MHz clock: workgroup 0's (phase << 56 | pass
  * start), element loop done, all flags seen, totals reduced, synchronisation
- * left, control done; the last workgroup's loop done and totals seen.  This
+ * left, control done; the last workgroup's loop done and totals seen (these
+ * two only in launches of more than 256 workgroups, where workgroup 0 reduces
+ * the pass alone and the others wait for its totals).  This
  * copies up to max_records records (8 values each) of the last launch to host
  * memory `out` and clears them; returns the number of records copied
  * (0 when tracing is off) or a negative status.  With max_records < 0 it
