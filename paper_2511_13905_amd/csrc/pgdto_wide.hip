@@ -619,25 +619,41 @@ __device__ __forceinline__ void wide_ncp(int mode, bool eqj, double h, double la
 // triangle) then overwrites the Jacobian sums in sh.tot, and one wave
 // solves the two triangular systems with the unknowns in lanes.
 // Reads sh.lam, sh.h, sh.act, sh.phi; writes sh.delta.
+// Row sums of the control by 8 threads per row (thread t: row t / 8, terms
+// k = t % 8, t % 8 + 8, ...), added over the 8 threads with a fixed xor
+// pattern, so every thread of the row holds the same bits.
+__device__ __forceinline__ double row8_sum(double part) {
+  part += __shfl_xor(part, 1, 64);
+  part += __shfl_xor(part, 2, 64);
+  part += __shfl_xor(part, 4, 64);
+  return part;
+}
+
 __device__ void wide_direction(ShW& sh, double* J, int m) {
   const int tid = threadIdx.x;
   const double kappa = sh.kappa;
   const int mode = sh.ncp;
   if (tid < m) sh.delta[tid] = sh.act[tid] ? 0.0 : (mode == PGDTO_NCP_PAPER ? sh.phi[tid] : -sh.lam[tid]);
-  if (tid == 0) {
-    int p = 0;
-    for (int j = 0; j < m; ++j)
-      if (sh.act[j]) sh.sidx[p++] = j;
-    sh.np = p;
+  if (tid < 64) {
+    // active rows in index order: a ballot and a prefix count
+    const bool on = tid < m && sh.act[tid];
+    const uint64_t msk = __ballot(on);
+    if (on) sh.sidx[__popcll(msk & ((1ull << tid) - 1ull))] = tid;
+    if (tid == 0) sh.np = __popcll(msk);
   }
   __syncthreads();
   const int p = sh.np;
-  if (tid < p) {
-    const int j = sh.sidx[tid];
-    double rj = sh.h[j];
-    for (int k = 0; k < m; ++k)
-      if (!sh.act[k]) rj -= (J[pks(j, k, m)] + (j == k ? kappa : 0.0)) * sh.delta[k];
-    sh.rhs[tid] = rj;
+  {
+    // rhs_r = h_j - sum over inactive k of (J + kappa I)_jk delta_k, j = sidx[r]
+    const int r = tid >> 3, c = tid & 7;
+    double part = 0.0;
+    if (r < p) {
+      const int j = sh.sidx[r];
+      for (int k = c; k < m; k += 8)
+        if (!sh.act[k]) part = fma(J[pks(j, k, m)] + (j == k ? kappa : 0.0), sh.delta[k], part);
+    }
+    part = row8_sum(part);
+    if (r < p && c == 0) sh.rhs[r] = sh.h[sh.sidx[r]] - part;
   }
   const int a = tid >> 3, c0 = tid & 7;
   double K[8];
@@ -714,14 +730,14 @@ __device__ int wide_accept(ShW& sh, const double* lam_in, const double* h_in, do
     sh.act[j] = act;
   }
   __syncthreads();
-  if (tid == 0) {
-    double res = 0.0, p2 = 0.0;
-    for (int j = 0; j < m; ++j) {
-      res = fmax(res, sh.rowv[j]);
-      p2 += sh.phi[j] * sh.phi[j];
+  if (tid < 64) {
+    const double res = wave_max(tid < m ? sh.rowv[tid] : 0.0);
+    const double ph = tid < m ? sh.phi[tid] : 0.0;
+    const double p2 = wave_sum(ph * ph);
+    if (tid == 0) {
+      sh.res_inf = res;
+      sh.p2 = p2;
     }
-    sh.res_inf = res;
-    sh.p2 = p2;
   }
   wide_direction(sh, J, m);
   const bool stop = sh.res_inf <= sh.tol_n || sh.it >= sh.max_newton;
@@ -760,40 +776,42 @@ __device__ int wide_after_trial(ShW& sh, const WSync& W, double* J, int m) {
   enum { HALVE = 0, ACCEPT_TRIAL = 1, ACCEPT_BEST = 2, KEEP = 4 };
   const int tid = threadIdx.x;
   const double kappa = sh.kappa;
-  if (tid < m) {
-    const int j = tid;
-    const bool eqj = (sh.eq >> j) & 1ull;
-    const double c = J[pk(j, j, m)] + kappa;
-    double phi;
-    int act;
-    wide_ncp(sh.ncp, eqj, sh.htr[j], sh.pay[j], c, phi, act);
-    double row;
-    if (act) {
-      row = 0.0;
-      for (int k = 0; k < m; ++k) row += (J[pks(j, k, m)] + (j == k ? kappa : 0.0)) * sh.delta[k];
-    } else {
-      row = (sh.ncp == PGDTO_NCP_PAPER) ? sh.delta[j] : c * sh.delta[j];
+  {
+    // row j of J_Phi delta (8 threads per row), then Phi_j times it
+    const int j = tid >> 3, cc = tid & 7;
+    double phi = 0.0, part = 0.0, c = 0.0;
+    int act = 0;
+    if (j < m) {
+      const bool eqj = (sh.eq >> j) & 1ull;
+      c = J[pk(j, j, m)] + kappa;
+      wide_ncp(sh.ncp, eqj, sh.htr[j], sh.pay[j], c, phi, act);
+      if (act)
+        for (int k = cc; k < m; k += 8) part = fma(J[pks(j, k, m)] + (j == k ? kappa : 0.0), sh.delta[k], part);
     }
-    sh.phi[j] = phi;
-    sh.rowv[j] = phi * row;
+    part = row8_sum(part);
+    if (j < m && cc == 0) {
+      const double row = act ? part : ((sh.ncp == PGDTO_NCP_PAPER) ? sh.delta[j] : c * sh.delta[j]);
+      sh.phi[j] = phi;
+      sh.rowv[j] = phi * row;
+    }
   }
   __syncthreads();
-  if (tid == 0) {
-    double p2 = 0.0, gd = 0.0;
-    for (int j = 0; j < m; ++j) {
-      p2 += sh.phi[j] * sh.phi[j];
-      gd += sh.rowv[j];
+  if (tid < 64) {
+    const double ph = tid < m ? sh.phi[tid] : 0.0;
+    const double p2 = wave_sum(ph * ph);
+    const double gd = wave_sum(tid < m ? sh.rowv[tid] : 0.0);
+    if (tid == 0) {
+      const bool armijo = 0.5 * p2 <= sh.M0 - sh.c1 * sh.gamma * sh.phi2;
+      const bool curv = gd <= sh.c2 * sh.phi2;
+      const int hb = sh.have_best, ls = sh.ls + 1;
+      sh.ls = ls;
+      int dec;
+      if (armijo && curv) dec = ACCEPT_TRIAL;
+      else if (ls >= sh.max_ls) dec = hb ? ACCEPT_BEST : ACCEPT_TRIAL;
+      else dec = HALVE;
+      if (armijo && !hb) dec |= KEEP;
+      sh.decision = dec;
     }
-    const bool armijo = 0.5 * p2 <= sh.M0 - sh.c1 * sh.gamma * sh.phi2;
-    const bool curv = gd <= sh.c2 * sh.phi2;
-    const int hb = sh.have_best, ls = sh.ls + 1;
-    sh.ls = ls;
-    int dec;
-    if (armijo && curv) dec = ACCEPT_TRIAL;
-    else if (ls >= sh.max_ls) dec = hb ? ACCEPT_BEST : ACCEPT_TRIAL;
-    else dec = HALVE;
-    if (armijo && !hb) dec |= KEEP;
-    sh.decision = dec;
   }
   __syncthreads();
   const int dec = sh.decision;
