@@ -57,6 +57,9 @@ def parse():
                     help="row counts of the many-row coupled leg (wide kernel), comma separated; empty: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--wide-only", action="store_true",
+                    help="run only the many-row coupled leg (--wide-m): the command the wide kernel "
+                         "profiles are taken with")
     ap.add_argument("--single-only", action="store_true",
                     help="run only the one-instance launches (no batch, server or wide legs): the command "
                          "the one-instance kernel profiles are taken with")
@@ -80,10 +83,10 @@ MEASURED_TRAFFIC = {
 # the same for the wide coupled kernel's launches (one projection each), by row count
 # (profiles/k_solve_wide_f32_many_rows_hbm_traffic.md)
 WIDE_MEASURED_TRAFFIC = {
-    64: {"kernel_sha": "884988942cb77054", "bytes_per_launch": 20455012991, "read": 20305437750,
-         "written": 149575241},
-    32: {"kernel_sha": "884988942cb77054", "bytes_per_launch": 6722674577, "read": 6684039560,
-         "written": 38635017},
+    64: {"kernel_sha": "02848ea381ddf98d", "bytes_per_launch": 20462464119, "read": 20312890035,
+         "written": 149574085},
+    32: {"kernel_sha": "02848ea381ddf98d", "bytes_per_launch": 6704075485, "read": 6664916198,
+         "written": 39159287},
 }
 
 
@@ -218,7 +221,9 @@ def main():
     t_gen = time.perf_counter()
     wide_ms = [int(v) for v in args.wide_m.split(",") if v.strip()]
     wide_gen = (lambda: [_gen_wide(m) for m in wide_ms]) if wide_ms else None
-    if wl == "pgd_compliance":
+    if args.wide_only:
+        states, wide_insts = [], (wide_gen() if wide_gen else [])
+    elif wl == "pgd_compliance":
         states, wide_insts = generate(_gen_pgd, list(range(B)), workers, wide_gen)
     else:
         states, wide_insts = generate(_gen_proj, [(wl, s) for s in range(B)], workers, wide_gen)
@@ -226,7 +231,7 @@ def main():
 
     # the CPU oracle runs before the GPU is initialised (its process pool forks)
     cpu_line, refs = (None, [])
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.wide_only:
         cpu_line, refs = cpu_baseline(wl, states, args.cpu_seconds, workers, cpu)
 
     import numpy as np
@@ -241,6 +246,13 @@ def main():
 
     def T(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    if args.wide_only:
+        out = {"wide_rows": [wide_bench(ctx, p, ncand, args) for p, ncand in wide_insts]}
+        close_all()
+        torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
 
     is_pgd = wl == "pgd_compliance"
     if is_pgd:
