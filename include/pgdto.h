@@ -305,14 +305,18 @@ int pgdto_ctx_autotune(pgdto_ctx* ctx, int enable);
  * for a file that cannot be opened. */
 int pgdto_ctx_autotune_save(pgdto_ctx* ctx, const char* path);
 int pgdto_ctx_autotune_load(pgdto_ctx* ctx, const char* path);
-/* Two more environment variables read at context creation, for studies of
- * the launch (results do not depend on either, bitwise):
+/* Three more environment variables read at context creation, for studies
+ * of the launch (results do not depend on any of them, bitwise):
  *   PGDTO_GRID=k       one-instance launches use at most k workgroups (the
  *                      size of a server slot, traced in isolation);
  *   PGDTO_DOOR_WAIT=t  the kernel's arrival door waits at most t ticks of the
  *                      100 MHz clock for the whole grid before it closes
  *                      (default 3000 = 30 us; 0 closes it at the first
- *                      arrival, so that fewer workgroups take part). */
+ *                      arrival, so that fewer workgroups take part);
+ *   PGDTO_REDUCE_WG0=1 one-instance launches reduce each pass's tile partials
+ *                      in workgroup 0 alone, which publishes the totals with
+ *                      a go word (the form of launches of more than 256
+ *                      workgroups), instead of in every workgroup. */
 /* Workgroups and tiles of the context's last launch. */
 int pgdto_ctx_last_launch(pgdto_ctx* ctx, int32_t* grid, int32_t* tiles);
 

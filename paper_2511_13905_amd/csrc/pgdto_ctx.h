@@ -23,6 +23,7 @@ struct pgdto_ctx {
   std::unordered_map<uint64_t, int> tuned_grid;
   int forced_grid = 0;                        // set while a candidate is timed
   uint64_t door_wait = pgdto::DOOR_WAIT_DEFAULT;   // arrival-door wait of one-instance launches (100 MHz ticks)
+  int reduce_wg0 = 0;                         // one-instance launches: workgroup 0 reduces each pass alone
   // one-launch batches: per-slot workspace (grown on demand) and pinned
   // descriptor areas used in turn, each with the event of its last launch
   int bt_cap = 0;                             // co-resident workgroups of the batch kernel

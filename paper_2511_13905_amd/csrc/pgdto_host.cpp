@@ -134,6 +134,11 @@ extern "C" int pgdto_ctx_create(int device, pgdto_ctx** out) {
     // 0 closes it at the first arrival, so that late workgroups occur)
     const char* dv = getenv("PGDTO_DOOR_WAIT");
     if (dv && dv[0]) c->door_wait = (uint64_t)std::max(0LL, atoll(dv));
+    // PGDTO_REDUCE_WG0=1: one-instance launches take the reduction in which
+    // workgroup 0 alone sums the pass partials and publishes the totals (the
+    // form launches of more than ALLRED_MAX_WG workgroups use)
+    const char* rv = getenv("PGDTO_REDUCE_WG0");
+    c->reduce_wg0 = (rv && rv[0] && rv[0] != '0') ? 1 : 0;
   }
   {
     const char* tv = getenv("PGDTO_TRACE");
@@ -359,7 +364,7 @@ int run_launch(pgdto_ctx* c, Desc& d, hipStream_t s, void* result_dev, bool is_p
   d.door_wait = c->door_wait;
   // every workgroup reduces the pass partials itself (one round trip less per
   // pass than workgroup 0 publishing totals and a go word)
-  d.allred = grid <= ALLRED_MAX_WG ? 1 : 0;
+  d.allred = (grid <= ALLRED_MAX_WG && !c->reduce_wg0) ? 1 : 0;
   d.buf0 = 0;
   // an ordinary launch: the kernel's arrival door admits the workgroups that
   // are running together (normally all of them) and sends late ones home

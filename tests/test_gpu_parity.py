@@ -437,6 +437,52 @@ def test_graph_replay_pgd_step(ctx):
         assert og["alpha"] == oe["alpha"] and og["proj"]["lam"] == oe["proj"]["lam"], k
 
 
+def test_reduction_forms_give_the_same_bits(ctx):
+    """The two forms of the per-pass grid reduction, every workgroup summing
+    the tile partials itself (the default) and workgroup 0 summing them alone
+    and publishing the totals with a go word (PGDTO_REDUCE_WG0=1; the form
+    of launches above 256 workgroups), add the same partials in the same tile
+    order: every kind gives the same bits either way."""
+    import os
+    from paper_2511_13905_amd.api import Context, result_from_bytes
+    os.environ["PGDTO_REDUCE_WG0"] = "1"
+    try:
+        c0 = Context(0)
+    finally:
+        del os.environ["PGDTO_REDUCE_WG0"]
+    p64 = I.compliance_3d(9, n=120001)
+    p64.y = p64.y.astype(np.float64)
+    p64.A = p64.A.astype(np.float64)
+    probs = [I.compliance_3d(3, n=1_000_003), I.multi_material(5, fields=4, n_per=131_071),
+             I.volume_com(0, grid=(96, 48, 24)), I.volume_com(1, grid=(96, 48, 24)), p64]
+    say("reduction forms", [p.n for p in probs])
+    try:
+        for p in probs:
+            outs = []
+            for c in (c0, ctx):
+                m = torch.zeros((p.n + 31) // 32, dtype=torch.int32, device="cuda:0")
+                x, r = c.project(p.kind, dev(p.y), dev(p.A), p.b, p.lo, p.hi, p.C, offsets=p.offsets, free_mask=m)
+                torch.cuda.synchronize()
+                outs.append((x.cpu().numpy(), m.cpu().numpy(), r))
+            (x0, m0, r0), (x1, m1, r1) = outs
+            assert r0["error"] == 0 and r1["error"] == 0
+            assert np.array_equal(x0, x1) and np.array_equal(m0, m1), p.kind
+            assert r0["lam"] == r1["lam"] and r0["passes"] == r1["passes"] and r0["resid"] == r1["resid"], p.kind
+        st = I.pgd_compliance_3d(4, t=60, n=400_001)
+        pg = []
+        for c in (c0, ctx):
+            d = dev(st.d_prev)
+            x, out = c.pgd_step("single", dev(st.problem.A), dev(st.rho), dev(st.rho_prev), dev(st.grad),
+                                dev(st.grad_prev), d, st.g, st.G, st.t, I.LO, I.HI)
+            torch.cuda.synchronize()
+            pg.append((x.cpu().numpy(), d.cpu().numpy(), out))
+        assert np.array_equal(pg[0][0], pg[1][0]) and np.array_equal(pg[0][1], pg[1][1])
+        assert pg[0][2]["alpha"] == pg[1][2]["alpha"] and pg[0][2]["proj"]["lam"] == pg[1][2]["proj"]["lam"]
+        assert pg[0][2]["rel_change"] == pg[1][2]["rel_change"]
+    finally:
+        c0.close()
+
+
 def test_late_arrivals_give_the_same_bits(ctx):
     """An arrival door that closes at the first arrival (PGDTO_DOOR_WAIT=0)
     leaves most of the grid out: the participants solve every tile, late
