@@ -80,6 +80,16 @@ MEASURED_TRAFFIC = {
 }
 
 
+# the same for one-instance launches (bench.py --single-only; profiles/k_solve_*_hbm_traffic.md),
+# per launch, means over the timed launches of the workload's four instances
+SINGLE_MEASURED_TRAFFIC = {
+    "pgd_compliance": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 196673572},
+    "project_compliance": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 56449348},
+    "multimaterial": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 31279540},
+    "volcom": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 525688971},
+}
+
+
 # the same for the wide coupled kernel's launches (one projection each), by row count
 # (profiles/k_solve_wide_f32_many_rows_hbm_traffic.md)
 WIDE_MEASURED_TRAFFIC = {
@@ -566,6 +576,9 @@ def single_bench(ctx, insts, is_pgd, n, rows, args):
     mean_passes = sum(passes) / len(passes)
     pr = [(r["proj"] if is_pgd else r) for r in res]
     alg = sum(pgd_bytes(n, r) if is_pgd else proj_bytes(n, rows, r) for r in pr) / len(pr)
+    # HBM bytes the counters measured per launch (register-resident passes read nothing)
+    mt = SINGLE_MEASURED_TRAFFIC.get(args.workload)
+    tr_gbps = mt["bytes_per_launch"] / (mean_ms * 1e-3) / 1e9 if mt and mt["kernel_sha"] == kernel_sha() else None
     return {"launch": "pgdto_pgd_step_async" if is_pgd else "pgdto_project_async",
             "instances_rotated": R, "passes_mean": mean_passes, "grid_tiles": list(ctx.last_launch()),
             "warm_ms": {"mean": mean_ms, "p50": warm[len(warm) // 2], "p99": warm[-1]},
@@ -574,8 +587,11 @@ def single_bench(ctx, insts, is_pgd, n, rows, args):
             "elements_per_s": n / (mean_ms * 1e-3),
             "algorithmic_GBps": alg / (mean_ms * 1e-3) / 1e9,
             "algorithmic_frac": alg / (mean_ms * 1e-3) / HBM_PEAK,
+            "traffic_GBps": tr_gbps,
+            "traffic_frac": None if tr_gbps is None else tr_gbps * 1e9 / HBM_PEAK,
             "note": "one instance is latency-bound: its first tiles stay in registers across passes and "
-                    "the per-pass grid synchronisation dominates; the HBM fraction is that of the batch"}
+                    "the per-pass grid synchronisation dominates; algorithmic bytes count those passes as "
+                    "reads, traffic is what the HBM counters measured"}
 
 
 # ---------------------------------------------------------------- serving
