@@ -75,18 +75,18 @@ KERNEL_SRC = [os.path.join(CSRC, f) for f in ("pgdto_internal.h", "pgdto_device.
 WIDE_SRC = [os.path.join(CSRC, f) for f in ("pgdto_internal.h", "pgdto_device.h", "pgdto_wide.hip")]
 MEASURED_TRAFFIC = {
     # profiles/k_batch_f32_pgd_compliance_b16_hbm_traffic.md
-    "pgd_compliance": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 6598329222,
-                       "read": 5736206141, "written": 862123081, "instances": 16},
+    "pgd_compliance": {"kernel_sha": "2c988a558aedc463", "bytes_per_launch": 6713519145,
+                       "read": 5885478935, "written": 828040210, "instances": 16},
 }
 
 
 # the same for one-instance launches (bench.py --single-only; profiles/k_solve_*_hbm_traffic.md),
 # per launch, means over the timed launches of the workload's four instances
 SINGLE_MEASURED_TRAFFIC = {
-    "pgd_compliance": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 196673572},
-    "project_compliance": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 56449348},
-    "multimaterial": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 31279540},
-    "volcom": {"kernel_sha": "0eb66b42eb481b88", "bytes_per_launch": 525688971},
+    "pgd_compliance": {"kernel_sha": "2c988a558aedc463", "bytes_per_launch": 196753538},
+    "project_compliance": {"kernel_sha": "2c988a558aedc463", "bytes_per_launch": 56435242},
+    "multimaterial": {"kernel_sha": "2c988a558aedc463", "bytes_per_launch": 31294599},
+    "volcom": {"kernel_sha": "2c988a558aedc463", "bytes_per_launch": 518471577},
 }
 
 

@@ -239,8 +239,13 @@ __device__ __forceinline__ void solve_1d(Sh1D& sh, const Desc& d, int32_t* buf_e
 
   // Register residency: the first tile of this workgroup keeps its y (pgd:
   // rho~) and a slots in registers across passes when it has at most RS
-  // vector slots per thread; later passes then read no memory for it.
-  constexpr int RS = 8;
+  // vector slots per thread; later passes then read no memory for it.  The
+  // batch's streaming variant (NT) keeps none: there a workgroup owns about
+  // 16 tiles, residency would save 1/16 of the search reads, and the 64
+  // registers it holds through every pass cost more (a 16-instance pgd_step
+  // launch ran 1.1% faster without it).  A resident and a streamed tile give
+  // the same bits.
+  constexpr int RS = NT ? 1 : 8;
   T ry[RS][V], ra[RS][V];
   bool resident = false;
   uint32_t rbits = 0u;      // element-validity masks of the resident slots, V bits each
